@@ -1,0 +1,152 @@
+"""Brute-force NumPy checks that pin the C oracle (test infrastructure only).
+
+Each routine here is written from the paper's definitions by a different
+route than ``aderdg_oracle.c``:
+
+* ``dense_predictor``: the space-time system of eq. Picard for one cell of a
+  linear, constant-coefficient PDE, assembled as Kronecker products of 1-D
+  integrals computed exactly with ``numpy.polynomial`` (no Gauss rule, no
+  Picard iteration) and solved with ``numpy.linalg.solve``.
+* ``ck_time_average_1d``: the time average of the exact (Cauchy-Kowalevskaya /
+  Taylor) solution of a 1-D linear system from polynomial data,
+  sum_k (-dt A d/dx)^k / (k+1)! Q.
+* ``fv_rusanov_step``: the textbook first-order Rusanov finite-volume update,
+  which is what the scheme reduces to at N = 0.
+"""
+import math
+
+import numpy as np
+from numpy.polynomial import legendre as npleg
+
+
+def gl_nodes01(n):
+    """Gauss-Legendre nodes and weights mapped to [0, 1] (library routine)."""
+    x, w = npleg.leggauss(n)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def lagrange_polys(nodes):
+    """Lagrange polynomials on `nodes` (in [0,1]) as Legendre series in y = 2x - 1
+    (coefficients from the inverse Legendre-Vandermonde matrix, well conditioned
+    at Gauss points)."""
+    n = len(nodes)
+    Vm = npleg.legvander(2.0 * np.asarray(nodes) - 1.0, n - 1)
+    C = np.linalg.inv(Vm)          # column j: coefficients of psi_j
+    return [C[:, j].copy() for j in range(n)]
+
+
+def _val(c, x):
+    return npleg.legval(2.0 * x - 1.0, c)
+
+
+def _der(c):
+    return 2.0 * npleg.legder(c)   # d/dx = 2 d/dy
+
+
+def _integrate01(c):
+    ci = npleg.legint(c)
+    return 0.5 * (npleg.legval(1.0, ci) - npleg.legval(-1.0, ci))
+
+
+def one_d_integrals(n):
+    """Exact 1-D integrals on [0,1]: mass M, derivative-test G[k][l] = int psi_k psi_l',
+    and the time matrix T1[k][l] = psi_k(1) psi_l(1) - int psi_k' psi_l."""
+    xi, _ = gl_nodes01(n)
+    ps = lagrange_polys(xi)
+    dps = [_der(p) for p in ps]
+    mul = npleg.legmul
+    M = np.array([[_integrate01(mul(ps[k], ps[l])) for l in range(n)] for k in range(n)])
+    G = np.array([[_integrate01(mul(ps[k], dps[l])) for l in range(n)] for k in range(n)])
+    T1 = np.array([[_val(ps[k], 1.0) * _val(ps[l], 1.0)
+                    - _integrate01(mul(dps[k], ps[l])) for l in range(n)] for k in range(n)])
+    F0 = np.array([_val(p, 0.0) for p in ps])
+    return M, G, T1, F0, xi
+
+
+def _kron_all(mats):
+    out = np.ones((1, 1))
+    for m in mats:
+        out = np.kron(out, m)
+    return out
+
+
+def dense_predictor(Q, A_list, n, h, dt):
+    """Exact solution of the cell-local space-time system of eq. Picard for a
+    linear PDE q_t + sum_j A_j q_{x_j} = 0 with constant matrices A_j.
+
+    Q: [V][S] nodal state (S = n^d, x fastest).  Returns q: [n][V][S], the
+    space-time nodal values at the Gauss-Legendre time nodes.
+
+    Weak form divided by h^d: (T1 (x) Ms) q + (dt/h) sum_j (Mt (x) Gj (x) M..) A_j q
+    = (F0 (x) Ms) Q, with all 1-D integrals exact."""
+    d = len(A_list)
+    V = Q.shape[0]
+    M, G, T1, F0, _ = one_d_integrals(n)
+    # unknown ordering: (a, v, s) with s = i0 + n i1 + ..., i.e. kron order
+    # (time) x (var) x (i_{d-1}) x ... x (i_0)
+    def space_op(j, Mj):
+        mats = []
+        for dim in range(d - 1, -1, -1):
+            mats.append(Mj if dim == j else M)
+        return _kron_all(mats)
+    Ms = space_op(-1, None)
+    lhs = np.kron(T1, np.kron(np.eye(V), Ms))
+    for j, A in enumerate(A_list):
+        lhs = lhs + (dt / h) * np.kron(M, np.kron(A, space_op(j, G)))
+    rhs = np.kron(F0[:, None], np.kron(np.eye(V), Ms)) @ Q.reshape(-1)
+    q = np.linalg.solve(lhs, rhs)
+    return q.reshape(n, V, -1)
+
+
+def ck_time_average_1d(Q, A, n, h, dt):
+    """1-D: time average over [t, t+dt] of the exact solution from degree-N
+    nodal data, sum_{k=0}^{N} (-dt A d/dx)^k / (k+1)! Q, with d/dx the exact
+    derivative of the interpolating polynomial (built here from numpy's
+    polynomial derivative, not from the oracle's matrix)."""
+    xi, _ = gl_nodes01(n)
+    ps = lagrange_polys(xi)
+    # derivative matrix from exact polynomial derivatives
+    Dm = np.array([[_val(_der(ps[j]), xi[i]) for j in range(n)] for i in range(n)])
+    V = Q.shape[0]
+    op = np.kron(A, Dm) / h  # acts on (v, s)
+    term = Q.reshape(-1).copy()
+    out = np.zeros_like(term)
+    for k in range(n + V * n):  # series terminates (nilpotent); extra terms are exact zeros
+        out += term / math.factorial(k + 1)
+        term = -dt * (op @ term)
+    return out.reshape(V, n)
+
+
+def rusanov_flux(qm, qp, flux, speed):
+    """Textbook Rusanov flux 0.5 (F(q-) + F(q+)) - 0.5 s (q+ - q-)."""
+    s = np.maximum(speed(qm), speed(qp))
+    return 0.5 * (flux(qm) + flux(qp)) - 0.5 * s * (qp - qm)
+
+
+def fv_rusanov_step(U, dt, h, fluxes, speeds):
+    """First-order finite volumes, periodic, with Rusanov fluxes.
+
+    U: [V, C_{d-1}, ..., C_0] cell averages.  fluxes[j](U), speeds[j](U) act on
+    arrays with the variable axis first."""
+    d = U.ndim - 1
+    out = U.copy()
+    for j in range(d):
+        ax = U.ndim - 1 - j            # array axis of dimension j
+        Up = np.roll(U, -1, axis=ax)   # right neighbour
+        G = rusanov_flux(U, Up, fluxes[j], speeds[j])   # flux at the right face
+        Gm = np.roll(G, 1, axis=ax)                     # flux at the left face
+        out = out - dt / h * (G - Gm)
+    return out
+
+
+def step_matrix(oracle, dt, t=0.0):
+    """Assemble the (linear) one-step map of an oracle instance column by column."""
+    N = oracle.ncell * oracle.V * oracle.S
+    M = np.zeros((N, N))
+    for i in range(N):
+        e = np.zeros(N)
+        e[i] = 1.0
+        oracle.set_state(e.reshape(oracle.shape))
+        oracle.step(t, dt)
+        M[:, i] = oracle.get_state().reshape(-1)
+    return M
