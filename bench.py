@@ -1,0 +1,217 @@
+"""Throughput of the ADER-DG time step on one MI355X.
+
+Workload: 3-D linear elastic waves (9 variables), order N = 5 (6 Gauss-Legendre
+nodes per dimension), 64^3 periodic cells on the unit cube, rho = 2.7,
+cp = 6.0, cs = 3.464, planar P + S wave; C_CFL = 0.5 in
+dt = C h / (d (2N+1) lambda_max).  One step = predictor (Picard iteration),
+face projection, volume integral, Rusanov flux and corrector over all cells.
+
+The same K steps are timed for the all-FP64 path and for the predictor and
+volume contractions in FP32, BF16 and FP16 on the matrix cores (FP32
+accumulate; Picard time operator, time averages, flux/corrector and state in
+FP64).  `value` is the FP16 variant's cell-DOF updates/s (DOF = cells * n^3 * 9
+per step); every variant's throughput, speed-up over FP64 and L2 error
+(eq. L2gauss norm, relative) against the FP64 GPU run and the exact solution
+are in `runs`.  Inputs are resident in HBM before the timed region.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6e12, "fp32_valu": 157.3e12, "mfma_fp32": 157.3e12, "mfma_bf16": 2.5e15,
+        "mfma_fp16": 2.5e15, "hbm": 8.0e12}
+TOL = {"fp64": 1e-10, "fp32": 1e-6, "fp16": 1e-3, "bf16": 1e-2}
+HEADLINE = "fp16"
+
+
+def flux_flops(pde, d):
+    """Flops of one pointwise flux F_j (one direction, one node)."""
+    return {"acoustic": 2, "elastic": 8 if d == 3 else 5, "euler": 3 * d + 7, "swe": 3}[pde]
+
+
+def predictor_flops(pde, d, N, V, I):
+    """Algorithmic flops per cell of one predictor launch (sum-factorised, no
+    padding): returns (contraction flops that go to the matrix cores in the
+    mixed path, FP64 vector flops, pointwise-flux flops)."""
+    n = N + 1
+    S = n ** d
+    ST = n * S
+    F = S // n
+    deriv = I * d * 2 * n * ST * V            # D along x, y, z at every time slice
+    volume = d * 2 * n * S * V                # Kxi along x, y, z
+    time_op = I * 2 * n * ST * V              # q_a <- Q - dt sum_b Atau[a][b] R_b
+    adds = I * ST * V * ((d - 1) + 1 + 2)     # sum over directions, 1/h scale, final update
+    flux = I * ST * d * flux_flops(pde, d)
+    avg = 2 * ST * V + n * S * d * flux_flops(pde, d) + 2 * ST * d * V
+    faces = 2 * 2 * d * V * F * 2 * n
+    return deriv + volume, time_op + adds + avg + faces, flux
+
+
+def predictor_bytes(d, N, V, face_bytes):
+    n = N + 1
+    S = n ** d
+    F = S // n
+    return 2 * S * V * 8 + 2 * d * 2 * V * F * face_bytes
+
+
+def l2(W, h, d, A, B=None):
+    import torch
+    diff = A if B is None else A - B
+    return float(torch.sqrt((diff * diff * W[None, None, :]).sum() * h ** d))
+
+
+def cpu_baseline(sc, seconds=12.0, cells=8):
+    """The FP64 oracle on a periodic cells^3 sub-grid of the same problem (same
+    order, cell size and per-cell work), timed on the host cores."""
+    import oracle
+    h = (sc.hi[0] - sc.lo[0]) / sc.cells[0]
+    o = oracle.Oracle(sc.dim, sc.order, (cells,) * sc.dim, sc.lo, tuple(sc.lo[j] + cells * h for j in range(sc.dim)),
+                      sc.pde, sc.params)
+    o.set_state(sc.initial_state(o.node_coords()))
+    dt = o.max_dt(sc.cfl)
+    o.step(0.0, dt)  # warm-up
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.step(steps * dt, dt)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 50:
+            break
+    dof = o.ncell * o.S * o.V
+    return {"value": dof * steps / el, "unit": "cell-DOF updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d FP64 oracle steps of the same problem on a periodic %d^3-cell sub-grid "
+                      "(%d cells, same order and cell size), %.1f s" % (steps, cells, o.ncell, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="elastic3d_n5_64")
+    ap.add_argument("--variants", default="fp64,fp32,bf16,fp16")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the step is not sharded across GPUs in this build "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2504_06889_amd import inputs
+    from paper_2504_06889_amd.aderdg import Solver
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    sc = inputs.SCENARIOS[args.workload]
+    g = Solver.from_scenario(sc)
+    print("workload %s: %d cells, N=%d, V=%d, S=%d" % (sc.name, g.ncell, sc.order, g.V, g.S), file=sys.stderr,
+          flush=True)
+    Q0h = sc.initial_state(g.node_coords())
+    Q0 = torch.from_numpy(Q0h).cuda()
+    del Q0h
+    g.set_state(Q0)
+    dt = g.max_dt(sc.cfl)
+    W = torch.from_numpy(g.weights()).cuda()
+    dof = g.ncell * g.S * g.V
+    total_steps = args.warmup + args.steps
+    T = total_steps * dt
+    exact = torch.from_numpy(sc.initial_state(g.node_coords(), T)).cuda()
+    nexact = l2(W, g.h, g.d, exact)
+
+    runs = {}
+    states = {}
+    for p in args.variants.split(","):
+        prec = ("fp64", "fp64", "fp64") if p == "fp64" else (p, p, "fp64")
+        g.set_precisions(*prec)
+        g.set_state(Q0)
+        g.time = 0.0
+        g.step(dt, args.warmup)
+        torch.cuda.synchronize()
+        g.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(dt, args.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        tp, tc, nt = g.get_timing()
+        g.set_timing(False)
+        out = torch.empty(g.shape, dtype=torch.float64, device="cuda")
+        g.get_state(out)
+        states[p] = out
+        runs[p] = {"precisions": {"predictor": prec[0], "volume": prec[1], "flux": prec[2]},
+                   "ms_per_step": 1e3 * el / args.steps, "dof_per_s": dof * args.steps / el,
+                   "predictor_ms": tp / max(nt, 1), "corrector_ms": tc / max(nt, 1),
+                   "l2_rel_vs_exact": l2(W, g.h, g.d, out, exact) / nexact}
+        print("%s: %.3f ms/step (predictor %.3f, corrector %.3f)" % (
+            p, runs[p]["ms_per_step"], runs[p]["predictor_ms"], runs[p]["corrector_ms"]), file=sys.stderr,
+            flush=True)
+    if "fp64" in states:
+        nref = l2(W, g.h, g.d, states["fp64"])
+        for p in runs:
+            runs[p]["l2_rel_vs_fp64_gpu"] = l2(W, g.h, g.d, states[p], states["fp64"]) / nref
+            runs[p]["tolerance"] = TOL[p]
+            runs[p]["within_tolerance"] = bool(runs[p]["l2_rel_vs_fp64_gpu"] <= TOL[p])
+            runs[p]["speedup_vs_fp64"] = runs["fp64"]["ms_per_step"] / runs[p]["ms_per_step"]
+
+    # roofline of the dominant kernel (the predictor) for each variant
+    I = g.iters
+    mf, v64, fl = predictor_flops(sc.pde, sc.dim, sc.order, g.V, I)
+    for p in runs:
+        t = runs[p]["predictor_ms"] * 1e-3
+        total = (mf + v64 + fl) * g.ncell
+        if p == "fp64":
+            ideal = total / PEAK["fp64"]
+            bound = "alu"
+        else:
+            t_m = mf * g.ncell / PEAK["mfma_" + p]
+            t_v = v64 * g.ncell / PEAK["fp64"] + fl * g.ncell / PEAK["fp32_valu"]
+            ideal = t_m + t_v
+            bound = "mfma" if t_m > t_v else "alu"
+        hbm = predictor_bytes(sc.dim, sc.order, g.V, 8) * g.ncell
+        runs[p]["roofline"] = {
+            "bound": bound, "achieved": total / t / 1e12, "peak": total / ideal / 1e12, "unit": "TFLOP/s",
+            "frac": ideal / t, "traffic": None,
+            "flops_per_launch": total, "mfma_flops_per_launch": (mf * g.ncell if p != "fp64" else 0),
+            "hbm_bytes_per_launch": hbm, "hbm_GBps": hbm / t / 1e9}
+
+    head = HEADLINE if HEADLINE in runs else list(runs)[-1]
+    r = runs[head]
+    line = {
+        "metric": "cell-DOF updates/s, mixed vs FP64 GPU at stated L2 error; adjoint/forward time",
+        "value": r["dof_per_s"], "unit": "cell-DOF updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "%s-mfma+f64" % head if head != "fp64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: 3-D elastic waves, N=5, 64^3 periodic cells, planar P+S wave, "
+                               "predictor+volume contractions in %s on matrix cores (FP32 accumulate), "
+                               "Picard time operator, averages, flux/corrector and state FP64, "
+                               "C_CFL=%.2f, dt=%.6e" % (sc.name, head, sc.cfl, dt),
+                   "cells": g.ncell, "order": sc.order, "dof_per_step": dof, "picard_iters": I},
+        "roofline": r["roofline"],
+        "speedup_vs_fp64": r.get("speedup_vs_fp64"),
+        "l2_rel_vs_fp64_gpu": r.get("l2_rel_vs_fp64_gpu"), "tolerance": TOL.get(head),
+        "runs": runs,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+    txt = json.dumps(line)
+    print(txt, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(txt + "\n")
+
+
+if __name__ == "__main__":
+    main()

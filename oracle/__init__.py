@@ -80,6 +80,7 @@ def lib():
         L.or_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         L.or_cell_size.restype = ctypes.c_double
         L.or_cell_size.argtypes = [vp]
+        L.or_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -107,6 +108,11 @@ def basis(n):
     if rc != 0:
         raise ValueError("unsupported number of nodes %d" % n)
     return out
+
+
+def num_threads():
+    """OpenMP threads the oracle's loops use."""
+    return lib().or_num_threads()
 
 
 def nvars(pde, dim):

@@ -37,6 +37,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define MAXN OR_MAXN
 #define MAXV OR_MAXV
@@ -897,3 +900,13 @@ int or_info(const or_solver *s, int *out)
 }
 
 double or_cell_size(const or_solver *s) { return s->h; }
+
+/* Number of OpenMP threads the parallel loops use. */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -90,5 +90,6 @@ int or_step_cells(const or_solver *s, double t, double dt, int m, const int64_t 
 int or_sample_points(const or_solver *s, int npts, const double *xyz, int var, double *out);
 int or_info(const or_solver *s, int *out);
 double or_cell_size(const or_solver *s);
+int or_num_threads(void);
 
 #endif

@@ -1,0 +1,38 @@
+// Discrete adjoint of the ADER-DG step for acoustics with per-cell material.
+#pragma once
+#include <string>
+
+#include "common.h"
+
+namespace aderdg {
+
+struct AdjointArgs {
+    int cfg_pde, dim, order;
+    long ncell;
+    int cells[3];
+    const DevBasis *B;
+    PdeArgs pde;
+    double dt, t, inv_h, sigma;
+    int iters;
+    const double *Qn;
+    double *lam;
+    double *grad;
+    long src_cell;
+    const double *src_phi;
+    double src_f0, src_t0, src_amp;
+};
+
+// Device work buffers owned by a solver for the adjoint.
+struct AdjointWork {
+    void *lamface = nullptr;   // face restrictions of the incoming adjoint
+    void *fwdface = nullptr;   // forward face data of the step
+    double *lamout = nullptr;  // outgoing adjoint
+    size_t bytes_lamface = 0, bytes_fwdface = 0, bytes_lamout = 0;
+};
+
+int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::string &msg);
+void adjoint_free(AdjointWork &w);
+void receivers_adjoint(double *lam, int V, int S, int n, int dim, int nrec, const long *rcell, const double *rphi,
+                       const double *weight, hipStream_t st);
+
+}  // namespace aderdg

@@ -1,0 +1,565 @@
+// C ABI of the ADER-DG library (declared in include/aderdg.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "aderdg.h"
+#include "adjoint.h"
+#include "basis.h"
+#include "registry.h"
+
+using namespace aderdg;
+
+// ---------------------------------------------------------------------------
+// Kernel registry
+// ---------------------------------------------------------------------------
+namespace aderdg {
+static std::map<std::tuple<int, int, int>, KernelSet> &registry() {
+    static std::map<std::tuple<int, int, int>, KernelSet> r;
+    return r;
+}
+void register_kernels(int pde, int dim, int order, const KernelSet &ks) {
+    registry()[std::make_tuple(pde, dim, order)] = ks;
+}
+const KernelSet *find_kernels(int pde, int dim, int order) {
+    auto it = registry().find(std::make_tuple(pde, dim, order));
+    return it == registry().end() ? nullptr : &it->second;
+}
+}  // namespace aderdg
+
+// ---------------------------------------------------------------------------
+// Small utility kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v) { *p = v; }
+__global__ void k_fill_i32(int *p, int v) { *p = v; }
+
+__global__ __launch_bounds__(256) void k_nonfinite(const double *x, long n, int *flag) {
+    int bad = 0;
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+        bad |= !isfinite(x[i]);
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0 && bad) atomicOr(flag, 1);
+}
+
+// p_h(x_r) = sum_s prod_j phi[r][j][i_j(s)] Q[cell_r][0][s]
+__global__ void k_receivers(const double *Q, int V, int S, int n, int dim, int nrec, const long *rcell,
+                            const double *rphi, double *out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrec) return;
+    const double *q = Q + rcell[r] * V * S;
+    const double *ph = rphi + (long)r * 3 * kMaxN;
+    double acc = 0.0;
+    for (int s = 0; s < S; s++) {
+        double w = ph[s % n];
+        if (dim > 1) w *= ph[kMaxN + (s / n) % n];
+        if (dim > 2) w *= ph[2 * kMaxN + s / (n * n)];
+        acc += w * q[s];
+    }
+    out[r] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Solver object
+// ---------------------------------------------------------------------------
+struct aderdg_solver {
+    aderdg_config cfg;
+    int n, d, V, S, F, iters;
+    long ncell;
+    double h, t = 0.0;
+    hipStream_t stream;
+    const KernelSet *ks;
+    DevBasis hB;
+    DevBasis *dB = nullptr;
+    double *dQ = nullptr;
+    void *dFaces = nullptr;
+    size_t face_elems = 0;
+    double *dMat = nullptr;
+    double *dSrcPhi = nullptr;
+    long src_cell = -1;
+    double src_f0 = 0, src_t0 = 0, src_amp = 0;
+    int nrec = 0;
+    long *dRecCell = nullptr;
+    double *dRecPhi = nullptr;
+    unsigned long long *dScalar = nullptr;
+    int *dFlag = nullptr;
+    int prec[4] = {0, 0, 0, 0};
+    AdjointWork adj;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // 3 events per timed step
+    int ev_used = 0;
+    std::string err;
+};
+
+#define FAIL(s, code, ...)                                                   \
+    do {                                                                     \
+        char _b[512];                                                        \
+        snprintf(_b, sizeof(_b), __VA_ARGS__);                               \
+        (s)->err = _b;                                                       \
+        return code;                                                         \
+    } while (0)
+
+#define HIPC(s, call)                                                                      \
+    do {                                                                                   \
+        hipError_t _e = (call);                                                            \
+        if (_e != hipSuccess) FAIL(s, ADERDG_E_DEVICE, "%s: %s", #call, hipGetErrorString(_e)); \
+    } while (0)
+
+static thread_local std::string g_create_err;
+
+static void free_all(aderdg_solver *s) {
+    for (auto e : s->ev) hipEventDestroy(e);
+    s->ev.clear();
+    hipFree(s->dB);
+    hipFree(s->dQ);
+    hipFree(s->dFaces);
+    hipFree(s->dMat);
+    hipFree(s->dSrcPhi);
+    hipFree(s->dRecCell);
+    hipFree(s->dRecPhi);
+    hipFree(s->dScalar);
+    hipFree(s->dFlag);
+    adjoint_free(s->adj);
+}
+
+static long state_elems(const aderdg_solver *s) { return s->ncell * (long)s->V * s->S; }
+
+static int nvars(int pde, int dim) {
+    switch (pde) {
+    case ADERDG_ACOUSTIC: return 1 + dim;
+    case ADERDG_ELASTIC: return dim * (dim + 1) / 2 + dim;
+    case ADERDG_EULER: return 2 + dim;
+    case ADERDG_SWE: return dim == 2 ? 4 : -1;
+    }
+    return -1;
+}
+
+extern "C" {
+
+aderdg_status aderdg_create(const aderdg_config *cfg, void *hip_stream, aderdg_solver **out) {
+    if (!cfg || !out) return ADERDG_E_INVALID;
+    *out = nullptr;
+    auto *s = new aderdg_solver();
+    s->cfg = *cfg;
+    s->stream = (hipStream_t)hip_stream;
+    if (cfg->dim < 2 || cfg->dim > 3) {
+        g_create_err = "dim must be 2 or 3";
+        delete s;
+        return ADERDG_E_INVALID;
+    }
+    s->d = cfg->dim;
+    s->n = cfg->order + 1;
+    s->V = nvars(cfg->pde, cfg->dim);
+    if (cfg->order < 0 || s->n > kMaxN || s->V < 0) {
+        g_create_err = "invalid order or pde/dim";
+        delete s;
+        return ADERDG_E_INVALID;
+    }
+    s->S = 1;
+    for (int i = 0; i < s->d; i++) s->S *= s->n;
+    s->F = s->S / s->n;
+    s->iters = cfg->picard_iters > 0 ? cfg->picard_iters : cfg->order + 1;
+    s->ncell = 1;
+    for (int i = 0; i < s->d; i++) {
+        if (cfg->cells[i] < 1) {
+            g_create_err = "cells must be positive";
+            delete s;
+            return ADERDG_E_INVALID;
+        }
+        s->ncell *= cfg->cells[i];
+    }
+    s->h = (cfg->hi[0] - cfg->lo[0]) / cfg->cells[0];
+    for (int i = 0; i < s->d; i++) {
+        const double hi = (cfg->hi[i] - cfg->lo[i]) / cfg->cells[i];
+        if (!(hi > 0) || std::fabs(hi - s->h) > 1e-12 * s->h) {
+            g_create_err = "cells must be cubes with positive size";
+            delete s;
+            return ADERDG_E_INVALID;
+        }
+    }
+    s->ks = find_kernels(cfg->pde, cfg->dim, cfg->order);
+    if (!s->ks) {
+        g_create_err = "no kernels built for this (pde, dim, order)";
+        delete s;
+        return ADERDG_E_UNSUPPORTED;
+    }
+    if (!build_basis(s->n, s->hB)) {
+        g_create_err = "basis construction failed";
+        delete s;
+        return ADERDG_E_INVALID;
+    }
+    s->face_elems = (size_t)s->ncell * s->d * 2 * 2 * s->V * s->F;
+    hipError_t e = hipSuccess;
+    e = hipMalloc(&s->dB, sizeof(DevBasis));
+    if (e == hipSuccess) e = hipMalloc(&s->dQ, sizeof(double) * state_elems(s));
+    if (e == hipSuccess) e = hipMalloc(&s->dFaces, sizeof(double) * s->face_elems);
+    if (e == hipSuccess) e = hipMalloc(&s->dScalar, sizeof(unsigned long long) * 4);
+    if (e == hipSuccess) e = hipMalloc(&s->dFlag, sizeof(int) * 4);
+    if (e != hipSuccess) {
+        g_create_err = std::string("device allocation failed: ") + hipGetErrorString(e);
+        free_all(s);
+        delete s;
+        return ADERDG_E_OOM;
+    }
+    e = hipMemcpy(s->dB, &s->hB, sizeof(DevBasis), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemsetAsync(s->dQ, 0, sizeof(double) * state_elems(s), s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->dFlag, 0, sizeof(int) * 4, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        g_create_err = std::string("device initialisation failed: ") + hipGetErrorString(e);
+        free_all(s);
+        delete s;
+        return ADERDG_E_DEVICE;
+    }
+    *out = s;
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_destroy(aderdg_solver *s) {
+    if (!s) return ADERDG_OK;
+    hipStreamSynchronize(s->stream);
+    free_all(s);
+    delete s;
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_set_state(aderdg_solver *s, const double *Q, int is_device) {
+    if (!s) return ADERDG_E_INVALID;
+    if (!Q) FAIL(s, ADERDG_E_INVALID, "null state pointer");
+    const size_t bytes = sizeof(double) * state_elems(s);
+    if (is_device) {
+        HIPC(s, hipMemcpyAsync(s->dQ, Q, bytes, hipMemcpyDeviceToDevice, s->stream));
+    } else {
+        HIPC(s, hipMemcpyAsync(s->dQ, Q, bytes, hipMemcpyHostToDevice, s->stream));
+        HIPC(s, hipStreamSynchronize(s->stream));
+    }
+    return ADERDG_OK;
+}
+
+static aderdg_status check_finite(aderdg_solver *s, const double *x, long count, bool *ok) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, s->stream, s->dFlag, 0);
+    long g = (count + 255) / 256;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_nonfinite, dim3(g), dim3(256), 0, s->stream, x, count, s->dFlag);
+    int flag = 0;
+    HIPC(s, hipMemcpyAsync(&flag, s->dFlag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIPC(s, hipStreamSynchronize(s->stream));
+    *ok = flag == 0;
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_get_state(aderdg_solver *s, double *Q, int is_device) {
+    if (!s) return ADERDG_E_INVALID;
+    if (!Q) FAIL(s, ADERDG_E_INVALID, "null state pointer");
+    const size_t bytes = sizeof(double) * state_elems(s);
+    HIPC(s, hipMemcpyAsync(Q, s->dQ, bytes, is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           s->stream));
+    bool ok = true;
+    aderdg_status st = check_finite(s, s->dQ, state_elems(s), &ok);
+    if (st != ADERDG_OK) return st;
+    if (!ok) FAIL(s, ADERDG_E_NONFINITE, "state holds NaN or Inf");
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_set_material(aderdg_solver *s, const double *c, int is_device) {
+    if (!s) return ADERDG_E_INVALID;
+    if (!c) FAIL(s, ADERDG_E_INVALID, "null material pointer");
+    if (s->cfg.pde != ADERDG_ACOUSTIC) FAIL(s, ADERDG_E_UNSUPPORTED, "per-cell material is for acoustics only");
+    if (!s->dMat) HIPC(s, hipMalloc(&s->dMat, sizeof(double) * s->ncell));
+    HIPC(s, hipMemcpyAsync(s->dMat, c, sizeof(double) * s->ncell,
+                           is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
+    if (!is_device) HIPC(s, hipStreamSynchronize(s->stream));
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_set_precision(aderdg_solver *s, int kernel, int prec) {
+    if (!s) return ADERDG_E_INVALID;
+    if (kernel < 0 || kernel > 3 || prec < 0 || prec > 3) FAIL(s, ADERDG_E_INVALID, "unknown kernel or precision");
+    if (kernel == ADERDG_K_STORAGE && prec != ADERDG_FP64) FAIL(s, ADERDG_E_UNSUPPORTED, "the state is stored in FP64");
+    if (kernel == ADERDG_K_PREDICTOR && !s->ks->pred[prec])
+        FAIL(s, ADERDG_E_UNSUPPORTED, "predictor precision %d not built for this (pde, dim, order)", prec);
+    s->prec[kernel] = prec;
+    return ADERDG_OK;
+}
+
+static PdeArgs pde_args(const aderdg_solver *s) {
+    PdeArgs p;
+    for (int i = 0; i < 8; i++) p.prm[i] = s->cfg.params[i];
+    p.mat = s->dMat;
+    return p;
+}
+
+aderdg_status aderdg_max_dt(aderdg_solver *s, double cfl, double *dt_out) {
+    if (!s || !dt_out) return ADERDG_E_INVALID;
+    if (!(cfl > 0)) FAIL(s, ADERDG_E_INVALID, "cfl must be positive");
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, s->stream, s->dScalar, 0ull);
+    s->ks->maxeig(s->dQ, pde_args(s), s->ncell, s->dScalar, s->stream);
+    unsigned long long bits = 0;
+    HIPC(s, hipMemcpyAsync(&bits, s->dScalar, sizeof(bits), hipMemcpyDeviceToHost, s->stream));
+    HIPC(s, hipStreamSynchronize(s->stream));
+    double lmax;
+    std::memcpy(&lmax, &bits, sizeof(double));
+    if (!(lmax > 0) || !std::isfinite(lmax)) FAIL(s, ADERDG_E_NONFINITE, "maximum wave speed is %g", lmax);
+    *dt_out = cfl * s->h / (s->d * (2.0 * s->cfg.order + 1.0) * lmax);
+    return ADERDG_OK;
+}
+
+static StepArgs step_args(aderdg_solver *s, double dt, double t) {
+    StepArgs a;
+    a.Q = s->dQ;
+    a.faces = s->dFaces;
+    a.B = s->dB;
+    a.pde = pde_args(s);
+    a.ncell = s->ncell;
+    for (int i = 0; i < 3; i++) a.cells[i] = i < s->d ? s->cfg.cells[i] : 1;
+    a.dt = dt;
+    a.inv_h = 1.0 / s->h;
+    a.sigma = dt / s->h;
+    a.t = t;
+    a.vol_prec = s->prec[ADERDG_K_VOLUME];
+    a.flux_prec = s->prec[ADERDG_K_FLUX];
+    a.iters = s->iters;
+    a.src_cell = s->src_cell;
+    a.src_phi = s->dSrcPhi;
+    a.src_f0 = s->src_f0;
+    a.src_t0 = s->src_t0;
+    a.src_amp = s->src_amp;
+    return a;
+}
+
+aderdg_status aderdg_step(aderdg_solver *s, double dt, int nsteps) {
+    if (!s) return ADERDG_E_INVALID;
+    if (!(dt > 0) || nsteps < 0) FAIL(s, ADERDG_E_INVALID, "dt must be positive and nsteps >= 0");
+    const StepFn pred = s->ks->pred[s->prec[ADERDG_K_PREDICTOR]];
+    const StepFn corr = s->ks->corr[s->prec[ADERDG_K_FLUX]];
+    for (int k = 0; k < nsteps; k++) {
+        StepArgs a = step_args(s, dt, s->t + k * dt);
+        hipEvent_t *e = nullptr;
+        if (s->timing) {
+            if ((size_t)(s->ev_used + 3) > s->ev.size()) {
+                for (int i = 0; i < 3 * 64; i++) {
+                    hipEvent_t x;
+                    HIPC(s, hipEventCreate(&x));
+                    s->ev.push_back(x);
+                }
+            }
+            e = &s->ev[s->ev_used];
+            s->ev_used += 3;
+            HIPC(s, hipEventRecord(e[0], s->stream));
+        }
+        pred(a, s->stream);
+        if (e) HIPC(s, hipEventRecord(e[1], s->stream));
+        corr(a, s->stream);
+        if (e) HIPC(s, hipEventRecord(e[2], s->stream));
+    }
+    HIPC(s, hipGetLastError());
+    s->t += nsteps * dt;
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_set_timing(aderdg_solver *s, int enable) {
+    if (!s) return ADERDG_E_INVALID;
+    s->timing = enable != 0;
+    s->ev_used = 0;
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_get_timing(aderdg_solver *s, double *out) {
+    if (!s || !out) return ADERDG_E_INVALID;
+    HIPC(s, hipStreamSynchronize(s->stream));
+    double tp = 0.0, tc = 0.0;
+    for (int i = 0; i + 2 < s->ev_used; i += 3) {
+        float a = 0.f, b = 0.f;
+        HIPC(s, hipEventElapsedTime(&a, s->ev[i], s->ev[i + 1]));
+        HIPC(s, hipEventElapsedTime(&b, s->ev[i + 1], s->ev[i + 2]));
+        tp += a;
+        tc += b;
+    }
+    out[0] = tp;
+    out[1] = tc;
+    out[2] = s->ev_used / 3;
+    s->ev_used = 0;
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_set_time(aderdg_solver *s, double t) {
+    if (!s) return ADERDG_E_INVALID;
+    s->t = t;
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_get_time(const aderdg_solver *s, double *t) {
+    if (!s || !t) return ADERDG_E_INVALID;
+    *t = s->t;
+    return ADERDG_OK;
+}
+
+// Locate x: cell index and local coordinates in [0,1]^d.
+static bool locate(const aderdg_solver *s, const double *x, long *cell, double *loc) {
+    long c = 0, m = 1;
+    for (int i = 0; i < s->d; i++) {
+        const double u = (x[i] - s->cfg.lo[i]) / s->h;
+        long ci = (long)std::floor(u);
+        if (ci == s->cfg.cells[i] && u <= s->cfg.cells[i] + 1e-12) ci = s->cfg.cells[i] - 1;
+        if (ci < 0 || ci >= s->cfg.cells[i]) return false;
+        loc[i] = u - ci;
+        c += ci * m;
+        m *= s->cfg.cells[i];
+    }
+    *cell = c;
+    return true;
+}
+
+aderdg_status aderdg_set_source(aderdg_solver *s, const double x[3], double f0, double t0, double amp) {
+    if (!s || !x) return ADERDG_E_INVALID;
+    if (s->cfg.pde != ADERDG_ACOUSTIC) FAIL(s, ADERDG_E_UNSUPPORTED, "point sources are for acoustics only");
+    long cell;
+    double loc[3];
+    if (!locate(s, x, &cell, loc)) FAIL(s, ADERDG_E_INVALID, "source outside the domain");
+    std::vector<double> phi(s->S);
+    const double hd = std::pow(s->h, s->d);
+    for (int sn = 0; sn < s->S; sn++) {
+        double p = 1.0, W = 1.0;
+        int r = sn;
+        for (int i = 0; i < s->d; i++) {
+            const int k = r % s->n;
+            r /= s->n;
+            p *= lagrange_value(s->n, s->hB.xi, k, loc[i]);
+            W *= s->hB.w[k];
+        }
+        phi[sn] = p / (hd * W);
+    }
+    if (!s->dSrcPhi) HIPC(s, hipMalloc(&s->dSrcPhi, sizeof(double) * s->S));
+    HIPC(s, hipMemcpy(s->dSrcPhi, phi.data(), sizeof(double) * s->S, hipMemcpyHostToDevice));
+    s->src_cell = cell;
+    s->src_f0 = f0;
+    s->src_t0 = t0;
+    s->src_amp = amp;
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_set_receivers(aderdg_solver *s, int nrec, const double *xyz) {
+    if (!s || nrec < 0 || (nrec > 0 && !xyz)) return ADERDG_E_INVALID;
+    std::vector<long> cells(nrec);
+    std::vector<double> phi((size_t)nrec * 3 * kMaxN, 0.0);
+    for (int r = 0; r < nrec; r++) {
+        double loc[3];
+        if (!locate(s, xyz + 3 * r, &cells[r], loc)) FAIL(s, ADERDG_E_INVALID, "receiver %d outside the domain", r);
+        for (int i = 0; i < s->d; i++)
+            for (int k = 0; k < s->n; k++)
+                phi[(size_t)r * 3 * kMaxN + i * kMaxN + k] = lagrange_value(s->n, s->hB.xi, k, loc[i]);
+    }
+    hipFree(s->dRecCell);
+    hipFree(s->dRecPhi);
+    s->dRecCell = nullptr;
+    s->dRecPhi = nullptr;
+    s->nrec = nrec;
+    if (nrec == 0) return ADERDG_OK;
+    HIPC(s, hipMalloc(&s->dRecCell, sizeof(long) * nrec));
+    HIPC(s, hipMalloc(&s->dRecPhi, sizeof(double) * phi.size()));
+    HIPC(s, hipMemcpy(s->dRecCell, cells.data(), sizeof(long) * nrec, hipMemcpyHostToDevice));
+    HIPC(s, hipMemcpy(s->dRecPhi, phi.data(), sizeof(double) * phi.size(), hipMemcpyHostToDevice));
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_read_receivers(aderdg_solver *s, double *out, int is_device) {
+    if (!s || !out) return ADERDG_E_INVALID;
+    if (s->nrec == 0) return ADERDG_OK;
+    double *dst = out;
+    double *tmp = nullptr;
+    if (!is_device) {
+        HIPC(s, hipMalloc(&tmp, sizeof(double) * s->nrec));
+        dst = tmp;
+    }
+    hipLaunchKernelGGL(k_receivers, dim3((s->nrec + 63) / 64), dim3(64), 0, s->stream, s->dQ, s->V, s->S, s->n,
+                       s->d, s->nrec, s->dRecCell, s->dRecPhi, dst);
+    if (!is_device) {
+        hipError_t e = hipMemcpyAsync(out, tmp, sizeof(double) * s->nrec, hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        hipFree(tmp);
+        if (e != hipSuccess) FAIL(s, ADERDG_E_DEVICE, "receiver copy: %s", hipGetErrorString(e));
+    }
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_step_adjoint(aderdg_solver *s, double dt, double t, const double *Qn_dev, double *lam_dev,
+                                  double *grad_dev) {
+    if (!s || !Qn_dev || !lam_dev || !grad_dev) return ADERDG_E_INVALID;
+    if (!(dt > 0)) FAIL(s, ADERDG_E_INVALID, "dt must be positive");
+    AdjointArgs a;
+    a.cfg_pde = s->cfg.pde;
+    a.dim = s->d;
+    a.order = s->cfg.order;
+    a.ncell = s->ncell;
+    for (int i = 0; i < 3; i++) a.cells[i] = i < s->d ? s->cfg.cells[i] : 1;
+    a.B = s->dB;
+    a.pde = pde_args(s);
+    a.dt = dt;
+    a.t = t;
+    a.inv_h = 1.0 / s->h;
+    a.sigma = dt / s->h;
+    a.iters = s->iters;
+    a.Qn = Qn_dev;
+    a.lam = lam_dev;
+    a.grad = grad_dev;
+    a.src_cell = s->src_cell;
+    a.src_phi = s->dSrcPhi;
+    a.src_f0 = s->src_f0;
+    a.src_t0 = s->src_t0;
+    a.src_amp = s->src_amp;
+    std::string msg;
+    const int rc = adjoint_step(s->adj, a, s->stream, msg);
+    if (rc != 0) {
+        s->err = msg;
+        return (aderdg_status)rc;
+    }
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_receivers_adjoint(aderdg_solver *s, const double *weight_dev, double *lam_dev) {
+    if (!s || !weight_dev || !lam_dev) return ADERDG_E_INVALID;
+    if (s->nrec == 0) return ADERDG_OK;
+    receivers_adjoint(lam_dev, s->V, s->S, s->n, s->d, s->nrec, s->dRecCell, s->dRecPhi, weight_dev, s->stream);
+    HIPC(s, hipGetLastError());
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_nodes(int n, double *xi, double *w) {
+    if (n < 1 || n > kMaxN || !xi || !w) return ADERDG_E_INVALID;
+    gauss_legendre01(n, xi, w);
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_info(const aderdg_solver *s, long long *info) {
+    if (!s || !info) return ADERDG_E_INVALID;
+    info[0] = s->n;
+    info[1] = s->d;
+    info[2] = s->V;
+    info[3] = s->S;
+    info[4] = s->F;
+    info[5] = s->iters;
+    info[6] = s->ncell;
+    const int fp = s->prec[ADERDG_K_FLUX];
+    info[7] = (long long)(2 * s->d * 2 * s->V * s->F) * (fp == 0 ? 8 : (fp == 1 ? 4 : 2));
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_state_ptr(aderdg_solver *s, double **dev_ptr) {
+    if (!s || !dev_ptr) return ADERDG_E_INVALID;
+    *dev_ptr = s->dQ;
+    return ADERDG_OK;
+}
+
+const char *aderdg_last_error(const aderdg_solver *s) {
+    if (!s) return g_create_err.c_str();
+    return s->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,235 @@
+// Device-side building blocks of the ADER-DG step for gfx950 (MI355X):
+// compile-time shapes, precision conversions, basis constants and the PDE
+// systems of arXiv 2504.06889, Sec. 4.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace aderdg {
+
+constexpr int kMaxN = 8;  // nodes per dimension supported (orders 0..7)
+
+enum Prec { P64 = 0, P32 = 1, PBF16 = 2, PF16 = 3 };
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// ---------------------------------------------------------------------------
+// Shapes and launch geometry for (DIM, N)
+// ---------------------------------------------------------------------------
+template <int DIM, int N>
+struct Shape {
+    static constexpr int n = N + 1;
+    static constexpr int S = ipow(n, DIM);       // spatial nodes per cell
+    static constexpr int F = ipow(n, DIM - 1);   // nodes per face
+    // cells per workgroup: enough to fill >= 4 wavefronts of 64 lanes
+    static constexpr int CPB = S >= 256 ? 1 : (256 / S);
+    static constexpr int TPB = ((CPB * S + 63) / 64) * 64;
+};
+
+// ---------------------------------------------------------------------------
+// Basis constants (built on the host in FP64; see basis.cpp)
+// ---------------------------------------------------------------------------
+struct DevBasis {
+    double xi[kMaxN], w[kMaxN];
+    double D[kMaxN][kMaxN];     // D[i][k] = psi_k'(xi_i)
+    double Atau[kMaxN][kMaxN];  // Picard time operator K1^{-1} W
+    double Kxi[kMaxN][kMaxN];   // weak-form volume operator w_k' D[k'][k] / w_k
+    double F0[kMaxN], F1[kMaxN];  // psi(0), psi(1)
+    double L0[kMaxN], L1[kMaxN];  // face lifts psi(0)/w, psi(1)/w
+    // the same operators rounded to each contraction format (index Prec; the
+    // FP64 slot holds the FP32 rounding and is unused), stored as float
+    float Dp[4][kMaxN][kMaxN];
+    float Kxip[4][kMaxN][kMaxN];
+    float F0p[4][kMaxN], F1p[4][kMaxN], L0p[4][kMaxN], L1p[4][kMaxN];
+};
+
+// ---------------------------------------------------------------------------
+// Precision conversions (round-to-nearest-even)
+// ---------------------------------------------------------------------------
+template <int P> struct Store;  // storage element of a contraction input
+template <> struct Store<P64> { using T = double; };
+template <> struct Store<P32> { using T = float; };
+template <> struct Store<PBF16> { using T = __hip_bfloat16; };
+template <> struct Store<PF16> { using T = _Float16; };
+
+__device__ __forceinline__ double to_f(double x, double*) { return x; }
+
+template <int P>
+__device__ __forceinline__ typename Store<P>::T round_to(float x);
+template <> __device__ __forceinline__ double round_to<P64>(float x) { return (double)x; }
+template <> __device__ __forceinline__ float round_to<P32>(float x) { return x; }
+template <> __device__ __forceinline__ __hip_bfloat16 round_to<PBF16>(float x) { return __float2bfloat16(x); }
+template <> __device__ __forceinline__ _Float16 round_to<PF16>(float x) { return (_Float16)x; }
+
+__device__ __forceinline__ float widen(float x) { return x; }
+__device__ __forceinline__ float widen(__hip_bfloat16 x) { return __bfloat162float(x); }
+__device__ __forceinline__ float widen(_Float16 x) { return (float)x; }
+__device__ __forceinline__ double widen(double x) { return x; }
+
+// Face-value storage per FLUX precision
+template <int P> struct FaceT { using T = typename Store<P>::T; };
+
+// ---------------------------------------------------------------------------
+// Per-cell physical parameters
+// ---------------------------------------------------------------------------
+struct PdeArgs {
+    double prm[8];        // acoustic: rho, K | elastic: rho, lambda, mu | Euler: gamma | SWE: g
+    const double *mat;    // per-cell sound speed (acoustic), or null
+};
+
+// ---------------------------------------------------------------------------
+// PDE systems.  flux<T>(c, q, j, F): physical flux in direction j at one node;
+// speed<T>(c, q, j): largest |eigenvalue| in direction j.  `c` is the
+// per-cell coefficient block built by cell().
+// ---------------------------------------------------------------------------
+template <int DIM>
+struct Acoustic {  // eq. acoustic: p_t + K div v = 0, rho v_t + grad p = 0
+    static constexpr int V = 1 + DIM;
+    static constexpr bool kNCP = false;
+    static constexpr bool kLinear = true;
+    struct Coef { double K, irho, c; };
+    __device__ static Coef cell(const PdeArgs &a, long cell) {
+        Coef c;
+        double rho = a.prm[0];
+        double sp = a.mat ? a.mat[cell] : sqrt(a.prm[1] / rho);
+        c.K = rho * sp * sp;
+        if (!a.mat) c.K = a.prm[1];
+        c.irho = 1.0 / rho;
+        c.c = sp;
+        return c;
+    }
+    template <class T>
+    __device__ static void flux(const Coef &c, const T *q, int j, T *F) {
+        F[0] = (T)c.K * q[1 + j];
+#pragma unroll
+        for (int i = 0; i < DIM; i++) F[1 + i] = (i == j) ? q[0] * (T)c.irho : (T)0;
+    }
+    template <class T>
+    __device__ static T speed(const Coef &c, const T *, int) { return (T)c.c; }
+};
+
+template <int DIM>
+struct Elastic {  // eq. equations_of_motion, q_t + A_j q_{x_j} = 0
+    static constexpr int V = DIM * (DIM + 1) / 2 + DIM;
+    static constexpr int NS = DIM * (DIM + 1) / 2;
+    static constexpr bool kNCP = false;
+    static constexpr bool kLinear = true;
+    struct Coef { double lam, mu, irho, cp; };
+    __device__ static Coef cell(const PdeArgs &a, long) {
+        Coef c;
+        c.lam = a.prm[1];
+        c.mu = a.prm[2];
+        c.irho = 1.0 / a.prm[0];
+        c.cp = sqrt((a.prm[1] + 2.0 * a.prm[2]) / a.prm[0]);
+        return c;
+    }
+    __device__ static constexpr int sidx(int a, int b) {
+        return a == b ? a
+                      : (DIM == 2 ? 2
+                                  : ((a + b == 1) ? 3 : ((a + b == 3) ? 4 : 5)));  // xy, yz, xz
+    }
+    template <class T>
+    __device__ static void flux(const Coef &c, const T *q, int j, T *F) {
+        const T *v = q + NS;
+        const T lam = (T)c.lam, mu = (T)c.mu, ir = (T)c.irho;
+#pragma unroll
+        for (int a = 0; a < DIM; a++)
+#pragma unroll
+            for (int b = a; b < DIM; b++) {
+                const int k = sidx(a, b);
+                if (a == b)
+                    F[k] = -(a == j ? lam + (T)2 * mu : lam) * v[j];
+                else
+                    F[k] = (b == j) ? -mu * v[a] : ((a == j) ? -mu * v[b] : (T)0);
+            }
+#pragma unroll
+        for (int i = 0; i < DIM; i++) F[NS + i] = -q[sidx(i, j)] * ir;
+    }
+    template <class T>
+    __device__ static T speed(const Coef &c, const T *, int) { return (T)c.cp; }
+};
+
+template <int DIM>
+struct Euler {  // conserved (rho, rho v, E), ideal gas
+    static constexpr int V = 2 + DIM;
+    static constexpr bool kNCP = false;
+    static constexpr bool kLinear = false;
+    struct Coef { double g; };
+    __device__ static Coef cell(const PdeArgs &a, long) { return Coef{a.prm[0]}; }
+    template <class T>
+    __device__ static T pressure(const Coef &c, const T *q) {
+        T ke = 0;
+#pragma unroll
+        for (int i = 0; i < DIM; i++) ke += q[1 + i] * q[1 + i];
+        return ((T)c.g - (T)1) * (q[1 + DIM] - (T)0.5 * ke / q[0]);
+    }
+    template <class T>
+    __device__ static void flux(const Coef &c, const T *q, int j, T *F) {
+        const T p = pressure(c, q);
+        const T uj = q[1 + j] / q[0];
+        F[0] = q[1 + j];
+#pragma unroll
+        for (int i = 0; i < DIM; i++) F[1 + i] = q[1 + i] * uj + (i == j ? p : (T)0);
+        F[1 + DIM] = uj * (q[1 + DIM] + p);
+    }
+    template <class T>
+    __device__ static T speed(const Coef &c, const T *q, int j) {
+        const T p = pressure(c, q);
+        return fabs(q[1 + j] / q[0]) + sqrt((T)c.g * p / q[0]);
+    }
+};
+
+struct Swe {  // (h, hu, hv, b); pressure term as non-conservative g h grad(h+b)
+    static constexpr int V = 4;
+    static constexpr bool kNCP = true;
+    static constexpr bool kLinear = false;
+    struct Coef { double g; };
+    __device__ static Coef cell(const PdeArgs &a, long) { return Coef{a.prm[0]}; }
+    template <class T>
+    __device__ static void flux(const Coef &, const T *q, int j, T *F) {
+        const T uj = q[1 + j] / q[0];
+        F[0] = q[1 + j];
+        F[1] = q[1] * uj;
+        F[2] = q[2] * uj;
+        F[3] = (T)0;
+    }
+    template <class T>
+    __device__ static T speed(const Coef &c, const T *q, int j) {
+        return fabs(q[1 + j] / q[0]) + sqrt((T)c.g * q[0]);
+    }
+    // eta = h + b, whose reference derivative feeds the non-conservative term
+    template <class T>
+    __device__ static T ncp_input(const T *q) { return q[0] + q[3]; }
+};
+
+// ---------------------------------------------------------------------------
+// Node index helpers (node = i0 + n i1 + n^2 i2)
+// ---------------------------------------------------------------------------
+template <int n>
+__device__ __forceinline__ int coord(int s, int j) {
+    return j == 0 ? s % n : (j == 1 ? (s / n) % n : s / (n * n));
+}
+template <int n>
+__device__ __forceinline__ constexpr int stride(int j) {
+    return j == 0 ? 1 : (j == 1 ? n : n * n);
+}
+// face node index of node s for direction j (coordinate j removed)
+template <int n, int DIM>
+__device__ __forceinline__ int face_of(int s, int j) {
+    if (DIM == 2) return j == 0 ? s / n : s % n;
+    if (j == 0) return s / n;
+    if (j == 1) return (s % n) + n * (s / (n * n));
+    return s % (n * n);
+}
+// first node of the line through face node f in direction j
+template <int n>
+__device__ __forceinline__ int line_start(int f, int j) {
+    if (j == 0) return f * n;
+    if (j == 1) return (f % n) + (f / n) * n * n;
+    return f;
+}
+
+}  // namespace aderdg

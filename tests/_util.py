@@ -41,3 +41,43 @@ def run_oracle(o, sc, nsteps, dt, t0=0.0, Q0=None):
         Q0 = sc.initial_state(o.node_coords(), t0)
     o.set_state(Q0)
     return o.run(nsteps, dt, t0)
+
+
+def rel_l2(o, A, B):
+    """Relative L2 (eq. L2gauss norm) of A - B over B."""
+    return o.l2(A, B) / max(o.l2(B), 1e-300)
+
+
+def gpu_solver(sc, cells=None, prec=None, picard_iters=0):
+    from paper_2504_06889_amd.aderdg import Solver
+    s = Solver.from_scenario(sc, cells=cells, picard_iters=picard_iters)
+    if prec is not None:
+        s.set_precisions(*prec)
+    return s
+
+
+def run_both(oracle_mod, sc, cells, nsteps, dt=None, prec=("fp64", "fp64", "fp64"), noise=0.0,
+             material=None, source=None, seed=0, emulate=False):
+    """Same seeded input through the oracle (FP64 unless emulate) and the GPU path."""
+    o = make_oracle(oracle_mod, sc, cells, prec=prec if emulate else ("fp64",) * 3)
+    Q0 = sc.initial_state(o.node_coords())
+    if noise:
+        scale = max(np.abs(Q0).max(), 1.0)
+        Q0 = Q0 + noise * scale * np.random.default_rng(seed).standard_normal(Q0.shape)
+    o.set_state(Q0)
+    if material is not None:
+        o.set_material(material)
+    if source is not None:
+        o.set_source(*source)
+    if dt is None:
+        dt = o.max_dt(sc.cfl)
+    A = o.run(nsteps, dt)
+    g = gpu_solver(sc, cells, prec=prec)
+    if material is not None:
+        g.set_material(material)
+    if source is not None:
+        g.set_source(*source)
+    g.set_state(Q0)
+    g.step(dt, nsteps)
+    B = g.get_state()
+    return o, A, B, dt, g
