@@ -192,6 +192,35 @@ __device__ __forceinline__ void lines_mfma(const typename Store<P>::T *X, float 
 }
 
 // ---------------------------------------------------------------------------
+// Picard line buffers.  Lines are numbered ((cb*DIM + j)*NV + v)*F + f: block
+// cell cb, direction j, variable v (NV = V, plus eta for the non-conservative
+// term), face node f.
+//  FP64:  position-major X[k][line] with an odd pitch NLP (conflict-free
+//         column access by consecutive lines), separate input and output.
+//  other: line-major F[line][NB] (NB = 4 or 8 positions, zero padded) in the
+//         contraction format, so that a lane's 4 MFMA operand values are one
+//         8-byte load; FP32 results in the same layout.
+// ---------------------------------------------------------------------------
+template <class Pde, int DIM, int N, int PP>
+struct PicardLayout {
+    using Sh = Shape<DIM, N>;
+    static constexpr int n = Sh::n, F = Sh::F, CPB = Sh::CPB;
+    static constexpr int NV = Pde::kNCP ? Pde::V + 1 : Pde::V;
+    static constexpr int NL = CPB * DIM * NV * F;
+    static constexpr int NLP = NL | 1;
+    static constexpr int NB = n <= 4 ? 4 : 8;
+    static constexpr int LPR = 16 / NB;
+    static constexpr int LPT = 16 * LPR;
+    static constexpr int NTILE = (NL + LPT - 1) / LPT;
+    static constexpr int NLT = NTILE * LPT;
+    // element offset of position k on line `line`, and the offset between variables
+    __device__ static constexpr int elem(int line, int k) { return PP == P64 ? k * NLP + line : line * NB + k; }
+    static constexpr int VSTRIDE = PP == P64 ? F : F * NB;
+    static constexpr size_t bytes =
+        PP == P64 ? (size_t)2 * n * NLP * 8 : (size_t)NLT * NB * (sizeof(typename Store<PP>::T) + 4);
+};
+
+// ---------------------------------------------------------------------------
 // LDS budget of the predictor
 // ---------------------------------------------------------------------------
 template <class Pde, int DIM, int N, int PP>
@@ -200,14 +229,21 @@ struct PredLds {
     static constexpr int V = Pde::V;
     static constexpr int NV = Pde::kNCP ? V + 1 : V;
     static constexpr int CPB = Sh::CPB, S = Sh::S;
-    static constexpr size_t picard =
-        PP == P64 ? (size_t)CPB * DIM * NV * S * 8
-                  : (size_t)CPB * DIM * NV * S * (sizeof(typename Store<PP>::T) + 4);
+    static constexpr size_t picard = PicardLayout<Pde, DIM, N, PP>::bytes;
     // epilogue: qbar, fbar_j (double), volume staging (4-byte input + float output)
     static constexpr size_t epi = (size_t)CPB * V * S * (8 + 8 + 4 + 4);
     static constexpr size_t ncp = Pde::kNCP ? (size_t)CPB * DIM * S * 8 : 0;
     static constexpr size_t bytes0 = picard > epi ? picard : epi;
     static constexpr size_t bytes = bytes0 > ncp ? bytes0 : ncp;
+};
+
+// Target occupancy of the predictor: the lower-precision paths keep the
+// Picard iterate in FP32 registers and can run two wavefronts per SIMD when
+// their LDS allows two workgroups per CU.
+template <class Pde, int DIM, int N, int PP>
+struct PredOcc {
+    static constexpr int waves =
+        (PP != P64 && PredLds<Pde, DIM, N, PP>::bytes * 2 <= 160 * 1024 && Shape<DIM, N>::TPB <= 256) ? 2 : 1;
 };
 
 // Volume contribution along direction j in a lower format PV: round fbar_j,
@@ -268,7 +304,8 @@ __device__ __forceinline__ double face_project(const double *src, int st, const 
 // Predictor + face projection + volume integral (Alg. 1, first traversal)
 // ---------------------------------------------------------------------------
 template <class Pde, int DIM, int N, int PP>
-__global__ __launch_bounds__((Shape<DIM, N>::TPB)) void k_predictor(StepArgs a) {
+__global__ __launch_bounds__((Shape<DIM, N>::TPB))
+__attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_predictor(StepArgs a) {
     using Sh = Shape<DIM, N>;
     using L = PredLds<Pde, DIM, N, PP>;
     constexpr int n = Sh::n, S = Sh::S, F = Sh::F, CPB = Sh::CPB, TPB = Sh::TPB;
@@ -288,126 +325,226 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) void k_predictor(StepArgs a) 
     double Qn[V];
 #pragma unroll
     for (int v = 0; v < V; v++) Qn[v] = active ? a.Q[(cell * V + v) * S + s] : 1.0;
-    double q[n][V];
-#pragma unroll
-    for (int t = 0; t < n; t++)
-#pragma unroll
-        for (int v = 0; v < V; v++) q[t][v] = Qn[v];
+    // The final Picard iterate is q_a = Qn - dt acc[a] (acc of the last
+    // iteration); the epilogue evaluates it on the fly from acc.
 
     const bool src_here = active && cell == a.src_cell;
     const double src_phi = src_here ? a.src_phi[s] : 0.0;
     const int iters = a.iters;
 
     // ---------------- Picard iterations (eq. Picard) ----------------
-    for (int it = 0; it < iters; it++) {
-        double acc[n][V];
+    // Per slice b: the node owners write F_j(q_b) into the line buffer, every
+    // line is differentiated, and the owners gather sum_j D_j F_j at their
+    // node and fold it into acc[a] += Atau[a][b] R_b.  Two barriers per slice:
+    // the line pass reads a buffer the owners do not touch until the next
+    // slice's first barrier, and writes one they only read after the second.
+    using PL = PicardLayout<Pde, DIM, N, PP>;
+    double acc[n][V];
+    // per-thread offset of its node in each direction's lines (variable 0)
+    int po[DIM];
+#pragma unroll
+    for (int j = 0; j < DIM; j++) {
+        const int line0 = ((cb * DIM + j) * NV) * F + face_of<n, DIM>(s, j);
+        po[j] = PL::elem(line0, coord<n>(s, j));
+    }
+    if constexpr (PP == P64) {
+        double *Xin = reinterpret_cast<double *>(smem);   // [n][NLP] position-major
+        double *Xout = Xin + n * PL::NLP;
+        double q[n][V];
 #pragma unroll
         for (int t = 0; t < n; t++)
 #pragma unroll
-            for (int v = 0; v < V; v++) acc[t][v] = 0.0;
-
+            for (int v = 0; v < V; v++) q[t][v] = Qn[v];
 #pragma unroll 1
-        for (int b = 0; b < n; b++) {
-            // q[b] with a run-time b: select with compile-time indices (keeps q in registers)
-            double qb[V];
+        for (int it = 0; it < iters; it++) {
 #pragma unroll
-            for (int v = 0; v < V; v++) qb[v] = q[0][v];
+            for (int t = 0; t < n; t++)
 #pragma unroll
-            for (int t = 1; t < n; t++)
-                if (t == b) {
+                for (int v = 0; v < V; v++) acc[t][v] = 0.0;
 #pragma unroll
-                    for (int v = 0; v < V; v++) qb[v] = q[t][v];
-                }
-            double R[V];
-#pragma unroll
-            for (int v = 0; v < V; v++) R[v] = 0.0;
-            if constexpr (PP == P64) {
-                double *fb = reinterpret_cast<double *>(smem);  // [CPB][DIM][NV][S]
-                // padding cells store zeros so that no stale LDS bits enter a line pass
+            for (int b = 0; b < n; b++) {
                 if (slot) {
 #pragma unroll
                     for (int j = 0; j < DIM; j++) {
                         double Fv[V];
-                        Pde::flux(coef, qb, j, Fv);
+                        Pde::flux(coef, q[b], j, Fv);
 #pragma unroll
-                        for (int v = 0; v < V; v++) fb[((cb * DIM + j) * NV + v) * S + s] = active ? Fv[v] : 0.0;
+                        for (int v = 0; v < V; v++) Xin[po[j] + v * PL::VSTRIDE] = active ? Fv[v] : 0.0;
                         if constexpr (Pde::kNCP)
-                            fb[((cb * DIM + j) * NV + V) * S + s] = active ? Pde::ncp_input(qb) : 0.0;
+                            Xin[po[j] + V * PL::VSTRIDE] = active ? Pde::ncp_input(q[b]) : 0.0;
                     }
                 }
                 __syncthreads();
-                lines_fp64<n, S, F>(fb, CPB * DIM * NV, B->D, [](int blk_) { return (blk_ / NV) % DIM; },
-                                    tid, TPB);
+                for (int Ln = tid; Ln < PL::NL; Ln += TPB) {
+                    double x[n];
+#pragma unroll
+                    for (int k = 0; k < n; k++) x[k] = Xin[k * PL::NLP + Ln];
+#pragma unroll
+                    for (int i = 0; i < n; i++) {
+                        double y = 0.0;
+#pragma unroll
+                        for (int k = 0; k < n; k++) y = fma(B->D[i][k], x[k], y);
+                        Xout[i * PL::NLP + Ln] = y;
+                    }
+                }
                 __syncthreads();
                 if (active) {
+                    double R[V];
 #pragma unroll
                     for (int v = 0; v < V; v++) {
                         double r = 0.0;
 #pragma unroll
-                        for (int j = 0; j < DIM; j++) r += fb[((cb * DIM + j) * NV + v) * S + s];
+                        for (int j = 0; j < DIM; j++) r += Xout[po[j] + v * PL::VSTRIDE];
                         R[v] = r;
                     }
                     if constexpr (Pde::kNCP) {
 #pragma unroll
-                        for (int j = 0; j < DIM; j++)
-                            R[1 + j] += coef.g * qb[0] * fb[((cb * DIM + j) * NV + V) * S + s];
+                        for (int j = 0; j < DIM; j++) R[1 + j] += coef.g * q[b][0] * Xout[po[j] + V * PL::VSTRIDE];
                     }
-                }
-            } else {
-                using T = typename Store<PP>::T;
-                T *fb = reinterpret_cast<T *>(smem);  // [CPB][DIM][NV][S] in format PP
-                float *rb = reinterpret_cast<float *>(smem + (size_t)CPB * DIM * NV * S * sizeof(T));
-                // padding cells store zeros: a tile row mixes lines of neighbouring
-                // cells, and a stale NaN times a zero block entry would poison them
-                if (slot) {
-                    float qf[V];
 #pragma unroll
-                    for (int v = 0; v < V; v++) qf[v] = (float)qb[v];
+                    for (int v = 0; v < V; v++) R[v] *= a.inv_h;
+                    if (src_here) R[0] -= ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
 #pragma unroll
-                    for (int j = 0; j < DIM; j++) {
-                        float Fv[V];
-                        Pde::flux(coef, qf, j, Fv);
+                    for (int t = 0; t < n; t++)
 #pragma unroll
-                        for (int v = 0; v < V; v++)
-                            fb[((cb * DIM + j) * NV + v) * S + s] = round_to<PP>(active ? Fv[v] : 0.0f);
-                        if constexpr (Pde::kNCP)
-                            fb[((cb * DIM + j) * NV + V) * S + s] = round_to<PP>(active ? Pde::ncp_input(qf) : 0.0f);
-                    }
-                }
-                __syncthreads();
-                lines_mfma<PP, n, S, F>(fb, rb, CPB * DIM * NV, B->Dp[PP],
-                                        [](int blk_) { return (blk_ / NV) % DIM; }, tid, TPB);
-                __syncthreads();
-                if (active) {
-#pragma unroll
-                    for (int v = 0; v < V; v++) {
-                        double r = 0.0;
-#pragma unroll
-                        for (int j = 0; j < DIM; j++) r += (double)rb[((cb * DIM + j) * NV + v) * S + s];
-                        R[v] = r;
-                    }
-                    if constexpr (Pde::kNCP) {
-#pragma unroll
-                        for (int j = 0; j < DIM; j++)
-                            R[1 + j] += (double)((float)coef.g * (float)qb[0] *
-                                                 rb[((cb * DIM + j) * NV + V) * S + s]);
-                    }
+                        for (int v = 0; v < V; v++) acc[t][v] = fma(B->Atau[t][b], R[v], acc[t][v]);
                 }
             }
 #pragma unroll
-            for (int v = 0; v < V; v++) R[v] *= a.inv_h;
-            if (src_here) R[0] -= ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
-#pragma unroll
             for (int t = 0; t < n; t++)
 #pragma unroll
-                for (int v = 0; v < V; v++) acc[t][v] = fma(B->Atau[t][b], R[v], acc[t][v]);
-            __syncthreads();
+                for (int v = 0; v < V; v++) q[t][v] = fma(-a.dt, acc[t][v], Qn[v]);
         }
+    } else {
+        using T = typename Store<PP>::T;
+        constexpr int NB = PL::NB, LPR = PL::LPR, LPT = PL::LPT;
+        T *Fb = reinterpret_cast<T *>(smem);                                    // [NLT][NB] line-major
+        float *Rb = reinterpret_cast<float *>(smem + (size_t)PL::NLT * NB * sizeof(T));  // [NLT][NB]
+        // zero padding (positions >= n and lines >= NL are never written)
+        for (int i = tid; i < PL::NLT * NB; i += TPB) Fb[i] = round_to<PP>(0.0f);
+        const int lane = tid & 63, wave = tid >> 6;
+        constexpr int NWAVE = TPB / 64;
+        const int r = lane & 15, g = lane >> 4;
+        // lane-constant operand offsets inside a tile (elements)
+        const int coff = (LPR * 4 * g + r / NB) * NB + r % NB;
+        const bool cvalid = (r % NB) < n;
+        // B operand: block-diagonal D^T, B[k][col] = D[col % NB][k % NB] on diagonal blocks
+        auto bval = [&](int k) -> float {
+            const int kb = k / NB, kk = k % NB, cbk = r / NB, cc = r % NB;
+            return (kb == cbk && kk < n && cc < n) ? B->Dp[PP][cc][kk] : 0.0f;
+        };
+        float qf[n][V];
 #pragma unroll
         for (int t = 0; t < n; t++)
 #pragma unroll
-            for (int v = 0; v < V; v++) q[t][v] = fma(-a.dt, acc[t][v], Qn[v]);
+            for (int v = 0; v < V; v++) qf[t][v] = (float)Qn[v];
+#pragma unroll 1
+        for (int it = 0; it < iters; it++) {
+#pragma unroll
+            for (int t = 0; t < n; t++)
+#pragma unroll
+                for (int v = 0; v < V; v++) acc[t][v] = 0.0;
+#pragma unroll 1
+            for (int b = 0; b < n; b++) {
+                float qb[V];
+#pragma unroll
+                for (int v = 0; v < V; v++) qb[v] = qf[0][v];
+#pragma unroll
+                for (int t = 1; t < n; t++)
+                    if (t == b) {
+#pragma unroll
+                        for (int v = 0; v < V; v++) qb[v] = qf[t][v];
+                    }
+                if (slot) {
+#pragma unroll
+                    for (int j = 0; j < DIM; j++) {
+                        float Fv[V];
+                        Pde::flux(coef, qb, j, Fv);
+#pragma unroll
+                        for (int v = 0; v < V; v++) Fb[po[j] + v * PL::VSTRIDE] = round_to<PP>(active ? Fv[v] : 0.0f);
+                        if constexpr (Pde::kNCP)
+                            Fb[po[j] + V * PL::VSTRIDE] = round_to<PP>(active ? Pde::ncp_input(qb) : 0.0f);
+                    }
+                }
+                __syncthreads();
+                if constexpr (PP == P32) {
+                    float bm[4];
+                    int aoff[4];
+#pragma unroll
+                    for (int m = 0; m < 4; m++) {
+                        const int k = 4 * m + g;
+                        bm[m] = bval(k);
+                        aoff[m] = (LPR * r + k / NB) * NB + k % NB;
+                    }
+                    for (int tile = wave; tile < PL::NTILE; tile += NWAVE) {
+                        const int base = tile * LPT * NB;
+                        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int m = 0; m < 4; m++)
+                            c = __builtin_amdgcn_mfma_f32_16x16x4f32(Fb[base + aoff[m]], bm[m], c, 0, 0, 0);
+                        if (cvalid) {
+#pragma unroll
+                            for (int e = 0; e < 4; e++) Rb[base + coff + LPR * NB * e] = c[e];
+                        }
+                    }
+                } else {
+                    const int aoff = (LPR * r + (4 * g) / NB) * NB + (4 * g) % NB;
+                    T bt[4];
+#pragma unroll
+                    for (int e = 0; e < 4; e++) bt[e] = round_to<PP>(bval(4 * g + e));
+                    for (int tile = wave; tile < PL::NTILE; tile += NWAVE) {
+                        const int base = tile * LPT * NB;
+                        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+                        if constexpr (PP == PBF16) {
+                            const i16x4 av = *reinterpret_cast<const i16x4 *>(Fb + base + aoff);
+                            i16x4 bv;
+#pragma unroll
+                            for (int e = 0; e < 4; e++) bv[e] = __builtin_bit_cast(short, bt[e]);
+                            c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
+                        } else {
+                            const f16x4 av = *reinterpret_cast<const f16x4 *>(Fb + base + aoff);
+                            f16x4 bv;
+#pragma unroll
+                            for (int e = 0; e < 4; e++) bv[e] = bt[e];
+                            c = __builtin_amdgcn_mfma_f32_16x16x16f16(av, bv, c, 0, 0, 0);
+                        }
+                        if (cvalid) {
+#pragma unroll
+                            for (int e = 0; e < 4; e++) Rb[base + coff + LPR * NB * e] = c[e];
+                        }
+                    }
+                }
+                __syncthreads();
+                if (active) {
+                    double R[V];
+#pragma unroll
+                    for (int v = 0; v < V; v++) {
+                        double rr = 0.0;
+#pragma unroll
+                        for (int j = 0; j < DIM; j++) rr += (double)Rb[po[j] + v * PL::VSTRIDE];
+                        R[v] = rr;
+                    }
+                    if constexpr (Pde::kNCP) {
+#pragma unroll
+                        for (int j = 0; j < DIM; j++)
+                            R[1 + j] += (double)((float)coef.g * qb[0] * Rb[po[j] + V * PL::VSTRIDE]);
+                    }
+#pragma unroll
+                    for (int v = 0; v < V; v++) R[v] *= a.inv_h;
+                    if (src_here) R[0] -= ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
+#pragma unroll
+                    for (int t = 0; t < n; t++)
+#pragma unroll
+                        for (int v = 0; v < V; v++) acc[t][v] = fma(B->Atau[t][b], R[v], acc[t][v]);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < n; t++)
+#pragma unroll
+                for (int v = 0; v < V; v++) qf[t][v] = (float)fma(-a.dt, acc[t][v], Qn[v]);
+        }
     }
+    __syncthreads();
 
     // ---------------- time averages (FP64) ----------------
     double qbar[V], fbar[DIM][V], nbar[V];
@@ -421,12 +558,15 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) void k_predictor(StepArgs a) 
 #pragma unroll
     for (int t = 0; t < n; t++) {
         const double wt = B->w[t];
+        double qt[V];
 #pragma unroll
-        for (int v = 0; v < V; v++) qbar[v] = fma(wt, q[t][v], qbar[v]);
+        for (int v = 0; v < V; v++) qt[v] = fma(-a.dt, acc[t][v], Qn[v]);
+#pragma unroll
+        for (int v = 0; v < V; v++) qbar[v] = fma(wt, qt[v], qbar[v]);
 #pragma unroll
         for (int j = 0; j < DIM; j++) {
             double Fv[V];
-            Pde::flux(coef, q[t], j, Fv);
+            Pde::flux(coef, qt, j, Fv);
 #pragma unroll
             for (int v = 0; v < V; v++) fbar[j][v] = fma(wt, Fv[v], fbar[j][v]);
         }
@@ -438,7 +578,7 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) void k_predictor(StepArgs a) 
         for (int t = 0; t < n; t++) {
             double qt[V];
 #pragma unroll
-            for (int v = 0; v < V; v++) qt[v] = q[t][v];
+            for (int v = 0; v < V; v++) qt[v] = fma(-a.dt, acc[t][v], Qn[v]);
             if (slot) {
 #pragma unroll
                 for (int j = 0; j < DIM; j++) eb[(cb * DIM + j) * S + s] = active ? Pde::ncp_input(qt) : 0.0;
