@@ -81,6 +81,8 @@ def lib():
         L.or_cell_size.restype = ctypes.c_double
         L.or_cell_size.argtypes = [vp]
         L.or_num_threads.restype = ctypes.c_int
+        L.or_adjoint_step.argtypes = [vp, dp, ctypes.c_double, ctypes.c_double, dp, dp, dp]
+        L.or_point_weights.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), dp]
         _lib = L
     return _lib
 
@@ -222,6 +224,27 @@ class Oracle:
         if lib().or_sample_points(self._h, xyz.shape[0], _ptr(pts), var, _ptr(out)) != 0:
             raise ValueError("point outside the domain")
         return out
+
+    def adjoint_step(self, Qn, t, dt, lam, grad):
+        """Reverse-mode adjoint of one step (acoustics with material): returns
+        (J^T lam, grad + d<lam, step(Qn)>/dc).  Qn is the state at the step start."""
+        Qn = np.ascontiguousarray(Qn, dtype=np.float64)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        mu = np.zeros_like(lam)
+        g = np.array(grad, dtype=np.float64, copy=True)
+        if lib().or_adjoint_step(self._h, _ptr(Qn), t, dt, _ptr(lam), _ptr(mu), _ptr(g)) != 0:
+            raise ValueError("adjoint needs acoustics with a material and FP64")
+        return mu, g
+
+    def point_weights(self, x):
+        """(cell, phi[S]) of point x: the receiver read-out is sum_k phi_k Q[cell, 0, k]."""
+        xx = np.zeros(3)
+        xx[:self.d] = x
+        cell = ctypes.c_int64()
+        w = np.zeros(self.S)
+        if lib().or_point_weights(self._h, _ptr(xx), ctypes.byref(cell), _ptr(w)) != 0:
+            raise ValueError("point outside the domain")
+        return cell.value, w
 
     def node_coords(self):
         """Physical coordinates of the nodes along each dimension, [C_j, n]."""

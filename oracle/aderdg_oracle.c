@@ -910,3 +910,226 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Discrete adjoint of one step for acoustics with per-cell sound speed.     */
+/*                                                                            */
+/* The step is affine in Q for fixed material (the point source adds a term  */
+/* independent of Q, though not of the material).  This routine is          */
+/* plain reverse mode over the forward operations of the step, in reverse    */
+/* order, with every Picard iterate stored: face integral (lift), Rusanov    */
+/* flux (including the speed s = max(c_L, c_R), ties to the left cell), face */
+/* projection, volume integral, time averages, Picard iterations.  The bulk  */
+/* modulus K = rho c^2 enters through F_j(q) = (K v_j, p/rho e_j).           */
+/*   mu   <- (d Q^{n+1} / d Q^n)^T lam                                       */
+/*   grad += d <lam, Q^{n+1}> / d c   (one entry per cell)                    */
+/* ------------------------------------------------------------------------ */
+
+/* y = A_j^T x at one node: A_j q = (K q[1+j], q[0]/rho e_j) */
+static void acoustic_flux_transpose(int d, double K, double rho, const double *x, int j, double *y)
+{
+    for (int v = 0; v <= d; v++) y[v] = 0.0;
+    y[0] = x[1 + j] / rho;
+    y[1 + j] = K * x[0];
+}
+
+int or_adjoint_step(or_solver *s, const double *Qn, double t, double dt, const double *lam,
+                    double *mu, double *grad)
+{
+    if (s->c.pde != OR_ACOUSTIC || !s->cmat) return -1;
+    if (s->c.prec[0] || s->c.prec[1] || s->c.prec[2]) return -1;
+    const int n = s->n, S = s->S, V = s->V, d = s->d, F = s->F, I = s->I;
+    const size_t VS = (size_t)V * S, FS = (size_t)d * 2 * V * F;
+    const double rho = s->c.params[0], sigma = dt / s->h, inv_h = 1.0 / s->h;
+    double Dt[MAXN * MAXN], Kxit[MAXN * MAXN], At[MAXN * MAXN];
+    for (int i = 0; i < n; i++)
+        for (int k = 0; k < n; k++) {
+            Dt[i * n + k] = s->D[k * n + i];
+            Kxit[i * n + k] = s->Kxi[k * n + i];
+            At[i * n + k] = s->Atau[k * n + i];
+        }
+    /* forward: iterates (q^0..q^I) per cell, time average and face data */
+    const size_t per_it = (size_t)n * VS;
+    double *iters = (double *)malloc(sizeof(double) * s->ncell * (I + 1) * per_it);
+    double *qbar = (double *)malloc(sizeof(double) * s->ncell * VS);
+    double *fq = (double *)malloc(sizeof(double) * s->ncell * FS);
+    if (!iters || !qbar || !fq) { free(iters); free(qbar); free(fq); return -1; }
+    /* The point source adds a Q-independent term, but it reaches the later
+     * Picard iterates and through them the K-dependent fluxes, so the
+     * recomputed iterates keep it. */
+#pragma omp parallel
+    {
+        cell_work w;
+        work_alloc(s, &w);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t c = 0; c < s->ncell; c++) {
+            const double *Qc = Qn + c * VS;
+            double *it = iters + (size_t)c * (I + 1) * per_it;
+            for (int a = 0; a < n; a++) memcpy(it + a * VS, Qc, VS * sizeof(double));
+            for (int r = 0; r < I; r++) {
+                double *qr = it + (size_t)r * per_it, *qn1 = it + (size_t)(r + 1) * per_it;
+                for (int b = 0; b < n; b++)
+                    slice_residual(s, c, qr + b * VS, t + s->xi[b] * dt, &w, w.R + b * VS);
+                for (int a = 0; a < n; a++)
+                    for (size_t i = 0; i < VS; i++) {
+                        double acc = 0.0;
+                        for (int b = 0; b < n; b++) acc += s->Atau[a * n + b] * w.R[b * VS + i];
+                        qn1[a * VS + i] = Qc[i] - dt * acc;
+                    }
+            }
+            const double *qI = it + (size_t)I * per_it;
+            double *qb = qbar + c * VS;
+            for (size_t i = 0; i < VS; i++) {
+                double acc = 0.0;
+                for (int a = 0; a < n; a++) acc += s->w[a] * qI[a * VS + i];
+                qb[i] = acc;
+            }
+            for (int j = 0; j < d; j++) {
+                int st = stride_of(j, n);
+                for (int side = 0; side < 2; side++) {
+                    const double *E = side ? s->F1 : s->F0;
+                    for (int v = 0; v < V; v++)
+                        for (int sn = 0; sn < S; sn++) {
+                            if (coord(sn, j, n) != 0) continue;
+                            int f = face_of(sn, j, n, d);
+                            fq[c * FS + (((size_t)j * 2 + side) * V + v) * F + f] =
+                                contract(n, E, qb + v * S + sn, st, OR_FP64);
+                        }
+                }
+            }
+        }
+        work_free(&w);
+    }
+    /* reverse, per cell */
+#pragma omp parallel
+    {
+        double *qbb = (double *)malloc(sizeof(double) * VS);      /* adjoint of qbar */
+        double *fbb = (double *)malloc(sizeof(double) * d * VS);  /* adjoint of fbar_j */
+        double *rho_a = (double *)malloc(sizeof(double) * n * VS);
+        double *rho_n = (double *)malloc(sizeof(double) * n * VS);
+        double *Rb = (double *)malloc(sizeof(double) * n * VS);
+        double *Y = (double *)malloc(sizeof(double) * VS);
+        double *Gb = (double *)malloc(sizeof(double) * V * F);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t c = 0; c < s->ncell; c++) {
+            const double *lc = lam + c * VS;
+            const double K = rho * s->cmat[c] * s->cmat[c];
+            double Kbar = 0.0;
+            /* volume: Qstar += sigma sum_j Kxi (x)_j fbar_j */
+            for (int j = 0; j < d; j++) {
+                apply_dir(s, Kxit, j, lc, fbb + (size_t)j * VS, V, OR_FP64);
+                for (size_t i = 0; i < VS; i++) fbb[(size_t)j * VS + i] *= sigma;
+            }
+            memset(qbb, 0, sizeof(double) * VS);
+            /* faces of this cell */
+            for (int j = 0; j < d; j++) {
+                int st = stride_of(j, n);
+                for (int side = 0; side < 2; side++) {
+                    int64_t nb = neighbour(s, c, j, side ? +1 : -1);
+                    int64_t cl = side ? c : nb, cr = side ? nb : c;
+                    const double *lL = lam + cl * VS, *lR = lam + cr * VS;
+                    const double sl = s->cmat[cl], sr = s->cmat[cr];
+                    const double sp = sl >= sr ? sl : sr;
+                    const int c_is_max = side ? (sl >= sr) : (sr > sl);
+                    double sbar = 0.0;
+                    for (int v = 0; v < V; v++)
+                        for (int sn = 0; sn < S; sn++) {
+                            if (coord(sn, j, n) != 0) continue;
+                            int f = face_of(sn, j, n, d);
+                            /* adjoint of the face flux G: Q_L -= sigma L1 G, Q_R += sigma L0 G */
+                            double g = sigma * (contract(n, s->L0, lR + v * S + sn, st, OR_FP64) -
+                                                contract(n, s->L1, lL + v * S + sn, st, OR_FP64));
+                            Gb[v * F + f] = g;
+                            const double qm = fq[cl * FS + (((size_t)j * 2 + 1) * V + v) * F + f];
+                            const double qp = fq[cr * FS + (((size_t)j * 2 + 0) * V + v) * F + f];
+                            sbar += -0.5 * g * (qp - qm);
+                        }
+                    if (c_is_max) Kbar += sbar / (2.0 * rho * s->cmat[c]); /* ds/dK of s = sqrt(K/rho) */
+                    /* G = 0.5 (f- + f+) - 0.5 s (q+ - q-): this cell's side */
+                    const double *E = side ? s->F1 : s->F0;
+                    const double qsign = side ? 0.5 * sp : -0.5 * sp;
+                    for (int v = 0; v < V; v++)
+                        for (int sn = 0; sn < S; sn++) {
+                            int i = coord(sn, j, n), f = face_of(sn, j, n, d);
+                            qbb[v * S + sn] += E[i] * qsign * Gb[v * F + f];
+                            fbb[((size_t)j * V + v) * S + sn] += E[i] * 0.5 * Gb[v * F + f];
+                        }
+                }
+            }
+            /* fbar_j = A_j qbar */
+            const double *qb = qbar + c * VS;
+            for (int j = 0; j < d; j++)
+                for (int sn = 0; sn < S; sn++) {
+                    double x[MAXV], y[MAXV];
+                    for (int v = 0; v < V; v++) x[v] = fbb[((size_t)j * V + v) * S + sn];
+                    acoustic_flux_transpose(d, K, rho, x, j, y);
+                    for (int v = 0; v < V; v++) qbb[v * S + sn] += y[v];
+                    Kbar += x[0] * qb[(1 + j) * S + sn];
+                }
+            /* qbar = sum_a w_a q^I_a */
+            double *mc = mu + c * VS;
+            for (size_t i = 0; i < VS; i++) mc[i] = lc[i];
+            for (int a = 0; a < n; a++)
+                for (size_t i = 0; i < VS; i++) rho_a[a * VS + i] = s->w[a] * qbb[i];
+            for (int a = 0; a < n; a++)
+                for (size_t i = 0; i < VS; i++) mc[i] += rho_a[a * VS + i];
+            /* Picard iterations in reverse: q^{r+1}_a = Q - dt sum_b Atau[a][b] R_b(q^r_b) */
+            const double *it = iters + (size_t)c * (I + 1) * per_it;
+            for (int r = I - 1; r >= 0; r--) {
+                for (int b = 0; b < n; b++)
+                    for (size_t i = 0; i < VS; i++) {
+                        double acc = 0.0;
+                        for (int a = 0; a < n; a++) acc += At[b * n + a] * rho_a[a * VS + i];
+                        Rb[b * VS + i] = -dt * acc;
+                    }
+                memset(rho_n, 0, sizeof(double) * n * VS);
+                const double *qr = it + (size_t)r * per_it;
+                for (int b = 0; b < n; b++)
+                    for (int j = 0; j < d; j++) {
+                        /* R_b = (1/h) sum_j D_j A_j q_b */
+                        apply_dir(s, Dt, j, Rb + b * VS, Y, V, OR_FP64);
+                        for (int sn = 0; sn < S; sn++) {
+                            double x[MAXV], y[MAXV];
+                            for (int v = 0; v < V; v++) x[v] = inv_h * Y[v * S + sn];
+                            acoustic_flux_transpose(d, K, rho, x, j, y);
+                            for (int v = 0; v < V; v++) rho_n[b * VS + v * S + sn] += y[v];
+                            Kbar += x[0] * qr[b * VS + (1 + j) * S + sn];
+                        }
+                    }
+                memcpy(rho_a, rho_n, sizeof(double) * n * VS);
+                for (int a = 0; a < n; a++)
+                    for (size_t i = 0; i < VS; i++) mc[i] += rho_a[a * VS + i];
+            }
+            grad[c] += Kbar * 2.0 * rho * s->cmat[c];
+        }
+        free(qbb); free(fbb); free(rho_a); free(rho_n); free(Rb); free(Y); free(Gb);
+    }
+    free(iters);
+    free(qbar);
+    free(fq);
+    return 0;
+}
+
+/* Nodal weights of point x: out[node] = phi_node(x) in the cell holding x. */
+int or_point_weights(const or_solver *s, const double *x, int64_t *cell_out, double *out)
+{
+    int64_t cell = 0, m = 1;
+    double loc[3];
+    for (int i = 0; i < s->d; i++) {
+        double u = (x[i] - s->c.lo[i]) / s->h;
+        int ci = (int)floor(u);
+        if (ci < 0 || ci >= s->c.cells[i]) return -1;
+        loc[i] = u - ci;
+        cell += ci * m;
+        m *= s->c.cells[i];
+    }
+    double psi[3][MAXN];
+    for (int i = 0; i < s->d; i++) lagrange_eval(s->n, s->xi, loc[i], psi[i]);
+    for (int sn = 0; sn < s->S; sn++) {
+        double phi = 1.0;
+        for (int i = 0; i < s->d; i++) phi *= psi[i][coord(sn, i, s->n)];
+        out[sn] = phi;
+    }
+    *cell_out = cell;
+    return 0;
+}

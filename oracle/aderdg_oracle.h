@@ -91,5 +91,8 @@ int or_sample_points(const or_solver *s, int npts, const double *xyz, int var, d
 int or_info(const or_solver *s, int *out);
 double or_cell_size(const or_solver *s);
 int or_num_threads(void);
+int or_adjoint_step(or_solver *s, const double *Qn, double t, double dt, const double *lam,
+                    double *mu, double *grad);
+int or_point_weights(const or_solver *s, const double *x, int64_t *cell_out, double *out);
 
 #endif
