@@ -3,10 +3,12 @@
 #include <string>
 
 #include "common.h"
+#include "kernels.h"
 
 namespace aderdg {
 
 struct AdjointArgs {
+    void (*pred)(const StepArgs &, hipStream_t);  // forward FP64 predictor of this shape
     int cfg_pde, dim, order;
     long ncell;
     int cells[3];

@@ -1,6 +1,14 @@
-// Discrete adjoint of the ADER-DG step (acoustics, per-cell sound speed).
-#include "adjoint.h"
+// Discrete adjoint of the ADER-DG step (acoustics, per-cell sound speed): host
+// dispatch of the three kernels of one adjoint step.
+//   1. k_lamface:   face restrictions L0^T lam, L1^T lam of the incoming adjoint;
+//   2. k_predictor: the forward step's face data from Qn (state untouched);
+//   3. k_adjoint:   per cell, Rusanov/face/volume adjoints, tangent predictor for
+//                   the material derivative, transposed Picard iterations.
+#include <map>
+#include <utility>
 
+#include "adjoint.h"
+#include "adjoint_kernels.h"
 #include "aderdg.h"
 
 namespace aderdg {
@@ -25,9 +33,110 @@ void receivers_adjoint(double *lam, int V, int S, int n, int dim, int nrec, cons
                        rcell, rphi, weight);
 }
 
-int adjoint_step(AdjointWork &, const AdjointArgs &, hipStream_t, std::string &msg) {
-    msg = "adjoint step not built";
-    return ADERDG_E_UNSUPPORTED;
+using LamFaceFn = void (*)(const double *, double *, long, const DevBasis *, hipStream_t);
+using AdjFn = void (*)(const AdjKArgs &, hipStream_t);
+
+template <int DIM, int N>
+struct AdjInstance {
+    static void lamface(const double *lam, double *out, long ncell, const DevBasis *B, hipStream_t st) {
+        const long total = ncell * DIM * 2 * (1 + DIM) * Shape<DIM, N>::F;
+        long g = (total + 255) / 256;
+        if (g > 65536) g = 65536;
+        hipLaunchKernelGGL((k_lamface<DIM, N>), dim3(g), dim3(256), 0, st, lam, out, ncell, B);
+    }
+    static void adjoint(const AdjKArgs &a, hipStream_t st) {
+        using Sh = Shape<DIM, N>;
+        hipLaunchKernelGGL((k_adjoint<DIM, N>), dim3((a.ncell + Sh::CPB - 1) / Sh::CPB), dim3(Sh::TPB), 0, st, a);
+    }
+};
+
+static const std::map<std::pair<int, int>, std::pair<LamFaceFn, AdjFn>> &adj_table() {
+    static const std::map<std::pair<int, int>, std::pair<LamFaceFn, AdjFn>> t = {
+        {{2, 1}, {&AdjInstance<2, 1>::lamface, &AdjInstance<2, 1>::adjoint}},
+        {{2, 2}, {&AdjInstance<2, 2>::lamface, &AdjInstance<2, 2>::adjoint}},
+        {{2, 3}, {&AdjInstance<2, 3>::lamface, &AdjInstance<2, 3>::adjoint}},
+        {{3, 1}, {&AdjInstance<3, 1>::lamface, &AdjInstance<3, 1>::adjoint}},
+        {{3, 2}, {&AdjInstance<3, 2>::lamface, &AdjInstance<3, 2>::adjoint}},
+        {{3, 5}, {&AdjInstance<3, 5>::lamface, &AdjInstance<3, 5>::adjoint}},
+    };
+    return t;
+}
+
+static int ensure(void **p, size_t *have, size_t need) {
+    if (*have >= need) return 0;
+    hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+    if (hipMalloc(p, need) != hipSuccess) return -1;
+    *have = need;
+    return 0;
+}
+
+int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::string &msg) {
+    auto it = adj_table().find(std::make_pair(a.dim, a.order));
+    if (it == adj_table().end() || !a.pred) {
+        msg = "adjoint not built for this (dim, order)";
+        return ADERDG_E_UNSUPPORTED;
+    }
+    const int V = 1 + a.dim;
+    int F = 1;
+    for (int i = 1; i < a.dim; i++) F *= a.order + 1;
+    const size_t lf = sizeof(double) * a.ncell * a.dim * 2 * V * F;
+    if (ensure(&w.lamface, &w.bytes_lamface, lf) || ensure(&w.fwdface, &w.bytes_fwdface, 2 * lf)) {
+        msg = "adjoint work allocation failed";
+        return ADERDG_E_OOM;
+    }
+    // 1. face restrictions of the incoming adjoint
+    it->second.first(a.lam, (double *)w.lamface, a.ncell, a.B, st);
+    // 2. forward face data of this step
+    StepArgs f;
+    f.Q = const_cast<double *>(a.Qn);
+    f.faces = w.fwdface;
+    f.B = a.B;
+    f.pde = a.pde;
+    f.ncell = a.ncell;
+    for (int i = 0; i < 3; i++) f.cells[i] = a.cells[i];
+    f.dt = a.dt;
+    f.inv_h = a.inv_h;
+    f.sigma = a.sigma;
+    f.t = a.t;
+    f.vol_prec = 0;
+    f.flux_prec = 0;
+    f.iters = a.iters;
+    f.write_state = 0;
+    f.src_cell = a.src_cell;
+    f.src_phi = a.src_phi;
+    f.src_f0 = a.src_f0;
+    f.src_t0 = a.src_t0;
+    f.src_amp = a.src_amp;
+    a.pred(f, st);
+    // 3. the adjoint proper
+    AdjKArgs k;
+    k.Qn = a.Qn;
+    k.lam = a.lam;
+    k.grad = a.grad;
+    k.lamface = (const double *)w.lamface;
+    k.fwdface = (const double *)w.fwdface;
+    k.B = a.B;
+    k.pde = a.pde;
+    k.ncell = a.ncell;
+    for (int i = 0; i < 3; i++) k.cells[i] = a.cells[i];
+    k.dt = a.dt;
+    k.inv_h = a.inv_h;
+    k.sigma = a.sigma;
+    k.t = a.t;
+    k.iters = a.iters;
+    k.src_cell = a.src_cell;
+    k.src_phi = a.src_phi;
+    k.src_f0 = a.src_f0;
+    k.src_t0 = a.src_t0;
+    k.src_amp = a.src_amp;
+    it->second.second(k, st);
+    if (hipGetLastError() != hipSuccess) {
+        msg = "adjoint kernel launch failed";
+        return ADERDG_E_DEVICE;
+    }
+    return 0;
 }
 
 void adjoint_free(AdjointWork &w) {

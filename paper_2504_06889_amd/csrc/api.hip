@@ -326,6 +326,7 @@ static StepArgs step_args(aderdg_solver *s, double dt, double t) {
     a.vol_prec = s->prec[ADERDG_K_VOLUME];
     a.flux_prec = s->prec[ADERDG_K_FLUX];
     a.iters = s->iters;
+    a.write_state = 1;
     a.src_cell = s->src_cell;
     a.src_phi = s->dSrcPhi;
     a.src_f0 = s->src_f0;
@@ -493,7 +494,12 @@ aderdg_status aderdg_step_adjoint(aderdg_solver *s, double dt, double t, const d
                                   double *grad_dev) {
     if (!s || !Qn_dev || !lam_dev || !grad_dev) return ADERDG_E_INVALID;
     if (!(dt > 0)) FAIL(s, ADERDG_E_INVALID, "dt must be positive");
+    if (s->cfg.pde != ADERDG_ACOUSTIC || !s->dMat)
+        FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint is built for acoustics with a per-cell material");
+    if (s->prec[ADERDG_K_PREDICTOR] || s->prec[ADERDG_K_VOLUME] || s->prec[ADERDG_K_FLUX])
+        FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint is FP64 only");
     AdjointArgs a;
+    a.pred = s->ks->pred[0];
     a.cfg_pde = s->cfg.pde;
     a.dim = s->d;
     a.order = s->cfg.order;

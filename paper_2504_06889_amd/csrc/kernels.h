@@ -32,6 +32,7 @@ struct StepArgs {
     double dt, inv_h, sigma, t;
     int vol_prec, flux_prec;
     int iters;            // Picard iterations
+    int write_state;      // 0: only the face data is produced (Q untouched)
     long src_cell;        // -1: no source
     const double *src_phi;
     double src_f0, src_t0, src_amp;
@@ -672,7 +673,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         __syncthreads();
     }
 
-    if (active) {
+    if (active && a.write_state) {
         double sbar = 0.0;
         if (src_here) {
 #pragma unroll
