@@ -92,6 +92,64 @@ def cpu_baseline(sc, seconds=12.0, cells=8):
                       "(%d cells, same order and cell size), %.1f s" % (steps, cells, o.ncell, el)}
 
 
+def adjoint_bench(steps=None, checkpoint=None, fd=True):
+    """Receiver-misfit gradient on the adjoint configuration: 3-D acoustics N=5,
+    64^3 cells on [0,20]^3, log-normal per-cell sound speed (mean 1.5, sigma 0.2,
+    seed 0), Ricker source f0=5 at the centre of cell (32,32,32), 64 receivers,
+    200 steps, checkpoint every 20.  Times the forward misfit and the backward
+    (adjoint) sweep and checks the gradient against central differences."""
+    import torch
+    from paper_2504_06889_amd import adjoint as adj
+    from paper_2504_06889_amd import inputs
+    from paper_2504_06889_amd.aderdg import Solver
+    sc = inputs.SCENARIOS["adjoint_acoustic3d_n5_64"]
+    ex = sc.extra
+    steps = steps or sc.steps
+    checkpoint = checkpoint or ex["checkpoint"]
+    g = Solver.from_scenario(sc)
+    c = torch.from_numpy(inputs.lognormal_speed(g.ncell, ex["c_mean"], ex["c_sigma"], ex["seed_c"])).cuda()
+    g.set_material(c)
+    dt = g.max_dt(sc.cfl)
+    xs = inputs.source_point(sc, g.h)
+    g.set_source(xs, ex["f0"], ex["t0"], ex["amp"])
+    g.set_receivers(inputs.receivers_near(xs, g.h, ex["nrec"], 2.5, ex["seed_rec"]))
+    Q0 = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
+    data = adj.record(g, torch.full_like(c, ex["c_mean"]), Q0, dt, steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    adj.record(g, c, Q0, dt, steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    cg = c.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = adj.misfit(cg, g, Q0, dt, steps, data, checkpoint)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    grad = cg.grad
+    out = {"workload": "adjoint_acoustic3d_n5_64: 3-D acoustics N=5, 64^3 cells, %d steps, checkpoint %d, "
+                       "64 receivers, Ricker f0=5, dt=%.6e" % (steps, checkpoint, dt),
+           "forward_ms": 1e3 * t_fwd, "forward_plain_ms": 1e3 * t_plain, "backward_ms": 1e3 * t_bwd,
+           "adjoint_over_forward": t_bwd / t_fwd, "misfit": float(J), "grad_norm": float(grad.norm())}
+    if fd:
+        rng = np.random.default_rng(7)
+        dc = torch.from_numpy(rng.standard_normal(g.ncell)).cuda()
+        eps = 1e-6 * float(c.norm()) / float(dc.norm())
+        with torch.no_grad():
+            jp = float(adj.misfit(c + eps * dc, g, Q0, dt, steps, data, checkpoint))
+            jm = float(adj.misfit(c - eps * dc, g, Q0, dt, steps, data, checkpoint))
+        fdv = (jp - jm) / (2 * eps)
+        ad = float(grad @ dc)
+        out.update({"fd_directional": fdv, "adjoint_directional": ad, "fd_rel_err": abs(fdv - ad) / abs(fdv),
+                    "fd_tolerance": 1e-6})
+    g.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +159,7 @@ def main():
     ap.add_argument("--variants", default="fp64,fp32,bf16,fp16")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -186,6 +245,9 @@ def main():
             "flops_per_launch": total, "mfma_flops_per_launch": (mf * g.ncell if p != "fp64" else 0),
             "hbm_bytes_per_launch": hbm, "hbm_GBps": hbm / t / 1e9}
 
+    g.close()
+    del states, Q0, exact
+    torch.cuda.empty_cache()
     head = HEADLINE if HEADLINE in runs else list(runs)[-1]
     r = runs[head]
     line = {
@@ -204,6 +266,11 @@ def main():
         "l2_rel_vs_fp64_gpu": r.get("l2_rel_vs_fp64_gpu"), "tolerance": TOL.get(head),
         "runs": runs,
     }
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_bench()
+        print("adjoint: %.1f ms forward, %.1f ms backward, ratio %.2f, fd rel err %.2e" % (
+            line["adjoint"]["forward_ms"], line["adjoint"]["backward_ms"], line["adjoint"]["adjoint_over_forward"],
+            line["adjoint"].get("fd_rel_err", float("nan"))), file=sys.stderr, flush=True)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
     txt = json.dumps(line)

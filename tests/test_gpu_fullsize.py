@@ -1,0 +1,78 @@
+"""Parity at the benchmark configurations' full sizes: one GPU step over the
+whole grid (the launch configuration the benchmark times) against the oracle's
+one-step result at sampled cells (corners and faces of the periodic box, so
+that every wrap-around neighbour is exercised, plus seeded random cells)."""
+import numpy as np
+import pytest
+
+from _util import gpu_solver, make_oracle
+from paper_2504_06889_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-6, "fp16": 1e-3, "bf16": 1e-2}
+
+
+def _sample_ids(cells, m=40, seed=0):
+    d = len(cells)
+    pick = []
+    for corner in range(2 ** d):
+        idx = [(cells[j] - 1) if (corner >> j) & 1 else 0 for j in range(d)]
+        pick.append(idx)
+    rng = np.random.default_rng(seed)
+    for _ in range(m):
+        pick.append([int(rng.integers(0, cells[j])) for j in range(d)])
+    ids = []
+    for idx in pick:
+        c, mult = 0, 1
+        for j in range(d):
+            c += idx[j] * mult
+            mult *= cells[j]
+        ids.append(c)
+    return np.unique(np.array(ids, dtype=np.int64))
+
+
+def _inputs(sc, o):
+    Q0 = sc.initial_state(o.node_coords())
+    material = source = None
+    if sc.ic == "zeros":  # adjoint configuration: seeded state, material and source
+        ex = sc.extra
+        Q0 = Q0 + 0.01 * np.random.default_rng(4).standard_normal(Q0.shape)
+        material = inputs.lognormal_speed(o.ncell, ex["c_mean"], ex["c_sigma"], ex["seed_c"])
+        source = (inputs.source_point(sc, o.h), ex["f0"], ex["t0"], ex["amp"])
+    return Q0, material, source
+
+
+CASES = [("elastic3d_n5_64", "fp64"), ("elastic3d_n5_64", "fp16"), ("elastic3d_n5_64", "bf16"),
+         ("elastic3d_n5_64", "fp32"), ("euler3d_n4_48", "fp64"), ("euler3d_n4_48", "bf16"),
+         ("swe2d_n6_512", "fp64"), ("swe2d_n6_512", "bf16"), ("adjoint_acoustic3d_n5_64", "fp64")]
+
+
+@pytest.mark.parametrize("name,p", CASES)
+def test_full_size_step_at_sampled_cells(oracle_mod, name, p):
+    sc = inputs.SCENARIOS[name]
+    print("case", name, p, sc.cells, flush=True)
+    o = make_oracle(oracle_mod, sc)
+    Q0, material, source = _inputs(sc, o)
+    o.set_state(Q0)
+    if material is not None:
+        o.set_material(material)
+        o.set_source(*source)
+    dt = o.max_dt(sc.cfl)
+    ids = _sample_ids(sc.cells, seed=len(name))
+    ref = o.step_cells(0.0, dt, ids)
+    del o
+    prec = ("fp64",) * 3 if p == "fp64" else (p, p, "fp64")
+    g = gpu_solver(sc, prec=prec)
+    if material is not None:
+        g.set_material(material)
+        g.set_source(*source)
+    g.set_state(Q0)
+    assert abs(g.max_dt(sc.cfl) - dt) <= 1e-14 * dt
+    g.step(dt, 1)
+    B = g.get_state()[ids]
+    err = np.abs(B - ref).max() / np.abs(ref).max()
+    rel = np.linalg.norm(B - ref) / np.linalg.norm(ref)
+    print("%s %s: sampled max rel %.3e, rel L2 %.3e" % (name, p, err, rel), flush=True)
+    assert np.all(np.isfinite(B))
+    assert rel <= TOL[p] and err <= 10 * TOL[p], (rel, err)
