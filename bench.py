@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (3 times), to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the step is not sharded across GPUs in this build "
@@ -172,6 +174,15 @@ def main():
     from paper_2504_06889_amd.aderdg import Solver
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        a_ = torch.ones(n, dtype=torch.float64, device="cuda")
+        b_ = torch.empty_like(a_)
+        for _ in range(3):
+            b_.copy_(a_)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+        return
     torch.cuda.set_device(0)
     sc = inputs.SCENARIOS[args.workload]
     g = Solver.from_scenario(sc)

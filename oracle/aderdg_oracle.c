@@ -553,11 +553,14 @@ static void slice_residual(const or_solver *s, int64_t cell, const double *qb, d
             for (int v = 0; v < V; v++) w->Fj[(j * V + v) * S + sn] = F[v];
         }
     }
-    /* divergence: sum over directions of D applied along that direction */
+    /* divergence: sum over directions of D applied along that direction; in
+     * emulated precision the sum over directions belongs to the same FP32
+     * accumulation as the contraction itself */
     for (int i = 0; i < V * S; i++) R[i] = 0.0;
     for (int j = 0; j < d; j++) {
         apply_dir(s, s->D, j, w->Fj + (size_t)j * V * S, w->tmp, V, p);
-        for (int i = 0; i < V * S; i++) R[i] += w->tmp[i];
+        for (int i = 0; i < V * S; i++)
+            R[i] = (p == OR_FP64) ? R[i] + w->tmp[i] : (double)((float)R[i] + (float)w->tmp[i]);
     }
     if (s->c.pde == OR_SWE) {
         for (int sn = 0; sn < S; sn++) {

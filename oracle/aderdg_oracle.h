@@ -29,7 +29,8 @@
  * Emulated precision (prec[0] predictor, prec[1] volume, prec[2] flux; values
  * OR_FP64/OR_FP32/OR_BF16/OR_FP16): the inputs of the contraction (data and
  * matrix) are rounded (FP32 first, then to the format, round-to-nearest-even),
- * products and sums in FP32, result widened to FP64.  Pointwise fluxes of the
+ * products and sums in FP32 (for the predictor, the sum over the d directions
+ * of the divergence too), result widened to FP64.  Pointwise fluxes of the
  * predictor then use FP32-rounded states; face values are stored rounded to
  * the flux format; the lift multiplies format-rounded inputs in FP32.  Time
  * averages, the Picard time operator and all state accumulation stay FP64.

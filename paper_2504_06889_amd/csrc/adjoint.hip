@@ -100,6 +100,7 @@ int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::stri
     f.inv_h = a.inv_h;
     f.sigma = a.sigma;
     f.t = a.t;
+    f.h = 1.0 / a.inv_h;
     f.vol_prec = 0;
     f.flux_prec = 0;
     f.iters = a.iters;

@@ -323,6 +323,7 @@ static StepArgs step_args(aderdg_solver *s, double dt, double t) {
     a.inv_h = 1.0 / s->h;
     a.sigma = dt / s->h;
     a.t = t;
+    a.h = s->h;
     a.vol_prec = s->prec[ADERDG_K_VOLUME];
     a.flux_prec = s->prec[ADERDG_K_FLUX];
     a.iters = s->iters;

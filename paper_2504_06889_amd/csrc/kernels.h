@@ -29,7 +29,7 @@ struct StepArgs {
     PdeArgs pde;
     long ncell;
     int cells[3];
-    double dt, inv_h, sigma, t;
+    double dt, inv_h, sigma, t, h;
     int vol_prec, flux_prec;
     int iters;            // Picard iterations
     int write_state;      // 0: only the face data is produced (Q untouched)
@@ -217,8 +217,16 @@ struct PicardLayout {
     // element offset of position k on line `line`, and the offset between variables
     __device__ static constexpr int elem(int line, int k) { return PP == P64 ? k * NLP + line : line * NB + k; }
     static constexpr int VSTRIDE = PP == P64 ? F : F * NB;
+    // FP32 output layout of the matrix-core path: line-major with a padded line
+    // stride OSTRIDE = NB + NB/4, so that the four lane groups of a tile (whose
+    // rows are 4*LPR lines apart) write to different LDS banks.
+    static constexpr int OSTRIDE = NB + NB / 4;
+    static constexpr int OVSTRIDE = F * OSTRIDE;
+    static constexpr int OTILE = LPT * OSTRIDE;
+    __device__ static constexpr int oelem(int line, int k) { return line * OSTRIDE + k; }
+    static constexpr size_t obytes = (size_t)NTILE * OTILE * 4;
     static constexpr size_t bytes =
-        PP == P64 ? (size_t)2 * n * NLP * 8 : (size_t)NLT * NB * (sizeof(typename Store<PP>::T) + 4);
+        PP == P64 ? (size_t)2 * n * NLP * 8 : (size_t)NLT * NB * sizeof(typename Store<PP>::T) + obytes;
 };
 
 // ---------------------------------------------------------------------------
@@ -326,8 +334,9 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     double Qn[V];
 #pragma unroll
     for (int v = 0; v < V; v++) Qn[v] = active ? a.Q[(cell * V + v) * S + s] : 1.0;
-    // The final Picard iterate is q_a = Qn - dt acc[a] (acc of the last
-    // iteration); the epilogue evaluates it on the fly from acc.
+    // The final Picard iterate is q_a = Qn - (dt/h) acc[a] (acc of the last
+    // iteration accumulates Atau applied to h R_b); the epilogue evaluates it
+    // on the fly from acc.
 
     const bool src_here = active && cell == a.src_cell;
     const double src_phi = src_here ? a.src_phi[s] : 0.0;
@@ -342,11 +351,12 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     using PL = PicardLayout<Pde, DIM, N, PP>;
     double acc[n][V];
     // per-thread offset of its node in each direction's lines (variable 0)
-    int po[DIM];
+    int po[DIM], pr[DIM];
 #pragma unroll
     for (int j = 0; j < DIM; j++) {
         const int line0 = ((cb * DIM + j) * NV) * F + face_of<n, DIM>(s, j);
         po[j] = PL::elem(line0, coord<n>(s, j));
+        pr[j] = PL::oelem(line0, coord<n>(s, j));
     }
     if constexpr (PP == P64) {
         double *Xin = reinterpret_cast<double *>(smem);   // [n][NLP] position-major
@@ -364,15 +374,16 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 for (int v = 0; v < V; v++) acc[t][v] = 0.0;
 #pragma unroll
             for (int b = 0; b < n; b++) {
+                // Padding cells (beyond ncell) hold Qn = 1 and never update it, so
+                // their fluxes are finite: no stale or non-finite bits enter the lines.
                 if (slot) {
 #pragma unroll
                     for (int j = 0; j < DIM; j++) {
                         double Fv[V];
                         Pde::flux(coef, q[b], j, Fv);
 #pragma unroll
-                        for (int v = 0; v < V; v++) Xin[po[j] + v * PL::VSTRIDE] = active ? Fv[v] : 0.0;
-                        if constexpr (Pde::kNCP)
-                            Xin[po[j] + V * PL::VSTRIDE] = active ? Pde::ncp_input(q[b]) : 0.0;
+                        for (int v = 0; v < V; v++) Xin[po[j] + v * PL::VSTRIDE] = Fv[v];
+                        if constexpr (Pde::kNCP) Xin[po[j] + V * PL::VSTRIDE] = Pde::ncp_input(q[b]);
                     }
                 }
                 __syncthreads();
@@ -390,50 +401,61 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 }
                 __syncthreads();
                 if (active) {
-                    double R[V];
+                    // h R_b: the 1/h of R_b is folded into sigma = dt/h of the update
 #pragma unroll
                     for (int v = 0; v < V; v++) {
                         double r = 0.0;
 #pragma unroll
                         for (int j = 0; j < DIM; j++) r += Xout[po[j] + v * PL::VSTRIDE];
-                        R[v] = r;
+                        if constexpr (Pde::kNCP) {
+                            if (v >= 1 && v <= DIM) r += coef.g * q[b][0] * Xout[po[v - 1] + V * PL::VSTRIDE];
+                        }
+                        if (v == 0 && src_here) r -= a.h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
+#pragma unroll
+                        for (int t = 0; t < n; t++) acc[t][v] = fma(B->Atau[t][b], r, acc[t][v]);
                     }
-                    if constexpr (Pde::kNCP) {
-#pragma unroll
-                        for (int j = 0; j < DIM; j++) R[1 + j] += coef.g * q[b][0] * Xout[po[j] + V * PL::VSTRIDE];
-                    }
-#pragma unroll
-                    for (int v = 0; v < V; v++) R[v] *= a.inv_h;
-                    if (src_here) R[0] -= ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
-#pragma unroll
-                    for (int t = 0; t < n; t++)
-#pragma unroll
-                        for (int v = 0; v < V; v++) acc[t][v] = fma(B->Atau[t][b], R[v], acc[t][v]);
                 }
             }
 #pragma unroll
             for (int t = 0; t < n; t++)
 #pragma unroll
-                for (int v = 0; v < V; v++) q[t][v] = fma(-a.dt, acc[t][v], Qn[v]);
+                for (int v = 0; v < V; v++) q[t][v] = fma(-a.sigma, acc[t][v], Qn[v]);
         }
     } else {
         using T = typename Store<PP>::T;
         constexpr int NB = PL::NB, LPR = PL::LPR, LPT = PL::LPT;
         T *Fb = reinterpret_cast<T *>(smem);                                    // [NLT][NB] line-major
-        float *Rb = reinterpret_cast<float *>(smem + (size_t)PL::NLT * NB * sizeof(T));  // [NLT][NB]
+        float *Rb = reinterpret_cast<float *>(smem + (size_t)PL::NLT * NB * sizeof(T));  // skewed [NLT][NB]
         // zero padding (positions >= n and lines >= NL are never written)
         for (int i = tid; i < PL::NLT * NB; i += TPB) Fb[i] = round_to<PP>(0.0f);
         const int lane = tid & 63, wave = tid >> 6;
         constexpr int NWAVE = TPB / 64;
         const int r = lane & 15, g = lane >> 4;
         // lane-constant operand offsets inside a tile (elements)
-        const int coff = (LPR * 4 * g + r / NB) * NB + r % NB;
-        const bool cvalid = (r % NB) < n;
+        // output offset in the skewed FP32 layout (lane groups g land on different banks)
+        const int coff_o = PL::oelem(LPR * 4 * g + r / NB, r % NB);
         // B operand: block-diagonal D^T, B[k][col] = D[col % NB][k % NB] on diagonal blocks
         auto bval = [&](int k) -> float {
             const int kb = k / NB, kk = k % NB, cbk = r / NB, cc = r % NB;
             return (kb == cbk && kk < n && cc < n) ? B->Dp[PP][cc][kk] : 0.0f;
         };
+        // constant B operands and lane offsets, set up once
+        float bm[4];      // FP32 path: B[4m+g][r]
+        int aoffm[4];     // FP32 path: A offsets of the four K=4 steps
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            const int k = 4 * m + g;
+            bm[m] = bval(k);
+            aoffm[m] = (LPR * r + k / NB) * NB + k % NB;
+        }
+        const int aoff = (LPR * r + (4 * g) / NB) * NB + (4 * g) % NB;  // 16-bit paths
+        typename std::conditional<PP == PBF16, i16x4, f16x4>::type bvec;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const T be = round_to<PP>(bval(4 * g + e));
+            if constexpr (PP == PBF16) bvec[e] = __builtin_bit_cast(short, be);
+            else if constexpr (PP == PF16) bvec[e] = be;
+        }
         float qf[n][V];
 #pragma unroll
         for (int t = 0; t < n; t++)
@@ -445,132 +467,111 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
             for (int t = 0; t < n; t++)
 #pragma unroll
                 for (int v = 0; v < V; v++) acc[t][v] = 0.0;
-#pragma unroll 1
+#pragma unroll
             for (int b = 0; b < n; b++) {
-                float qb[V];
-#pragma unroll
-                for (int v = 0; v < V; v++) qb[v] = qf[0][v];
-#pragma unroll
-                for (int t = 1; t < n; t++)
-                    if (t == b) {
-#pragma unroll
-                        for (int v = 0; v < V; v++) qb[v] = qf[t][v];
-                    }
+                const float *qb = qf[b];
+                // padding cells: finite fluxes of Qn = 1 (see the FP64 branch)
                 if (slot) {
 #pragma unroll
                     for (int j = 0; j < DIM; j++) {
                         float Fv[V];
                         Pde::flux(coef, qb, j, Fv);
 #pragma unroll
-                        for (int v = 0; v < V; v++) Fb[po[j] + v * PL::VSTRIDE] = round_to<PP>(active ? Fv[v] : 0.0f);
-                        if constexpr (Pde::kNCP)
-                            Fb[po[j] + V * PL::VSTRIDE] = round_to<PP>(active ? Pde::ncp_input(qb) : 0.0f);
+                        for (int v = 0; v < V; v++) Fb[po[j] + v * PL::VSTRIDE] = round_to<PP>(Fv[v]);
+                        if constexpr (Pde::kNCP) Fb[po[j] + V * PL::VSTRIDE] = round_to<PP>(Pde::ncp_input(qb));
                     }
                 }
                 __syncthreads();
                 if constexpr (PP == P32) {
-                    float bm[4];
-                    int aoff[4];
-#pragma unroll
-                    for (int m = 0; m < 4; m++) {
-                        const int k = 4 * m + g;
-                        bm[m] = bval(k);
-                        aoff[m] = (LPR * r + k / NB) * NB + k % NB;
-                    }
                     for (int tile = wave; tile < PL::NTILE; tile += NWAVE) {
                         const int base = tile * LPT * NB;
+                        const int obase = tile * PL::OTILE;
                         f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                         for (int m = 0; m < 4; m++)
-                            c = __builtin_amdgcn_mfma_f32_16x16x4f32(Fb[base + aoff[m]], bm[m], c, 0, 0, 0);
-                        if (cvalid) {
+                            c = __builtin_amdgcn_mfma_f32_16x16x4f32(Fb[base + aoffm[m]], bm[m], c, 0, 0, 0);
 #pragma unroll
-                            for (int e = 0; e < 4; e++) Rb[base + coff + LPR * NB * e] = c[e];
-                        }
+                        for (int e = 0; e < 4; e++) Rb[obase + coff_o + LPR * PL::OSTRIDE * e] = c[e];
                     }
                 } else {
-                    const int aoff = (LPR * r + (4 * g) / NB) * NB + (4 * g) % NB;
-                    T bt[4];
+                    // tiles of this wave in batches of TB: all operand loads, then the
+                    // independent MFMAs, then the stores, so that LDS and matrix-core
+                    // latencies overlap
+                    constexpr int TPW = (PL::NTILE + NWAVE - 1) / NWAVE;
+                    constexpr int TB = TPW < 4 ? TPW : 4;
 #pragma unroll
-                    for (int e = 0; e < 4; e++) bt[e] = round_to<PP>(bval(4 * g + e));
-                    for (int tile = wave; tile < PL::NTILE; tile += NWAVE) {
-                        const int base = tile * LPT * NB;
-                        f32x4 c = {0.f, 0.f, 0.f, 0.f};
-                        if constexpr (PP == PBF16) {
-                            const i16x4 av = *reinterpret_cast<const i16x4 *>(Fb + base + aoff);
-                            i16x4 bv;
+                    for (int k0 = 0; k0 < TPW; k0 += TB) {
+                        using VT = typename std::conditional<PP == PBF16, i16x4, f16x4>::type;
+                        VT av[TB];
+                        f32x4 cc[TB];
 #pragma unroll
-                            for (int e = 0; e < 4; e++) bv[e] = __builtin_bit_cast(short, bt[e]);
-                            c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
-                        } else {
-                            const f16x4 av = *reinterpret_cast<const f16x4 *>(Fb + base + aoff);
-                            f16x4 bv;
-#pragma unroll
-                            for (int e = 0; e < 4; e++) bv[e] = bt[e];
-                            c = __builtin_amdgcn_mfma_f32_16x16x16f16(av, bv, c, 0, 0, 0);
+                        for (int k = 0; k < TB; k++) {
+                            const int tile = wave + (k0 + k) * NWAVE;
+                            if (k0 + k < TPW && tile < PL::NTILE)
+                                av[k] = *reinterpret_cast<const VT *>(Fb + tile * LPT * NB + aoff);
                         }
-                        if (cvalid) {
 #pragma unroll
-                            for (int e = 0; e < 4; e++) Rb[base + coff + LPR * NB * e] = c[e];
+                        for (int k = 0; k < TB; k++) {
+                            const int tile = wave + (k0 + k) * NWAVE;
+                            if (k0 + k < TPW && tile < PL::NTILE) {
+                                f32x4 z = {0.f, 0.f, 0.f, 0.f};
+                                if constexpr (PP == PBF16)
+                                    cc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[k], bvec, z, 0, 0, 0);
+                                else
+                                    cc[k] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[k], bvec, z, 0, 0, 0);
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < TB; k++) {
+                            const int tile = wave + (k0 + k) * NWAVE;
+                            if (k0 + k < TPW && tile < PL::NTILE) {  // padding lanes store to unused slots
+                                const int obase = tile * PL::OTILE;
+#pragma unroll
+                                for (int e = 0; e < 4; e++) Rb[obase + coff_o + LPR * PL::OSTRIDE * e] = cc[k][e];
+                            }
                         }
                     }
                 }
                 __syncthreads();
                 if (active) {
-                    double R[V];
+                    // R_b[v] = (1/h) sum_j (D_j F_j)[v] (- source), folded straight into
+                    // acc[a][v] += Atau[a][b] R_b[v] one variable at a time
 #pragma unroll
                     for (int v = 0; v < V; v++) {
-                        double rr = 0.0;
+                        // the divergence sum over directions is part of the FP32
+                        // contraction; h R_b is accumulated (1/h folded into sigma)
+                        float rf = 0.0f;
 #pragma unroll
-                        for (int j = 0; j < DIM; j++) rr += (double)Rb[po[j] + v * PL::VSTRIDE];
-                        R[v] = rr;
+                        for (int j = 0; j < DIM; j++) rf += Rb[pr[j] + v * PL::OVSTRIDE];
+                        double rr = (double)rf;
+                        if constexpr (Pde::kNCP) {
+                            if (v >= 1 && v <= DIM)
+                                rr += (double)((float)coef.g * qb[0] * Rb[pr[v - 1] + V * PL::OVSTRIDE]);
+                        }
+                        if (v == 0 && src_here)
+                            rr -= a.h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
+#pragma unroll
+                        for (int t = 0; t < n; t++) acc[t][v] = fma(B->Atau[t][b], rr, acc[t][v]);
                     }
-                    if constexpr (Pde::kNCP) {
-#pragma unroll
-                        for (int j = 0; j < DIM; j++)
-                            R[1 + j] += (double)((float)coef.g * qb[0] * Rb[po[j] + V * PL::VSTRIDE]);
-                    }
-#pragma unroll
-                    for (int v = 0; v < V; v++) R[v] *= a.inv_h;
-                    if (src_here) R[0] -= ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
-#pragma unroll
-                    for (int t = 0; t < n; t++)
-#pragma unroll
-                        for (int v = 0; v < V; v++) acc[t][v] = fma(B->Atau[t][b], R[v], acc[t][v]);
                 }
             }
 #pragma unroll
             for (int t = 0; t < n; t++)
 #pragma unroll
-                for (int v = 0; v < V; v++) qf[t][v] = (float)fma(-a.dt, acc[t][v], Qn[v]);
+                for (int v = 0; v < V; v++) qf[t][v] = (float)fma(-a.sigma, acc[t][v], Qn[v]);
         }
     }
     __syncthreads();
 
     // ---------------- time averages (FP64) ----------------
-    double qbar[V], fbar[DIM][V], nbar[V];
+    // qbar here; the flux averages fbar_j are formed per direction below
+    double qbar[V], nbar[V];
 #pragma unroll
     for (int v = 0; v < V; v++) {
         qbar[v] = 0.0;
         nbar[v] = 0.0;
 #pragma unroll
-        for (int j = 0; j < DIM; j++) fbar[j][v] = 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t < n; t++) {
-        const double wt = B->w[t];
-        double qt[V];
-#pragma unroll
-        for (int v = 0; v < V; v++) qt[v] = fma(-a.dt, acc[t][v], Qn[v]);
-#pragma unroll
-        for (int v = 0; v < V; v++) qbar[v] = fma(wt, qt[v], qbar[v]);
-#pragma unroll
-        for (int j = 0; j < DIM; j++) {
-            double Fv[V];
-            Pde::flux(coef, qt, j, Fv);
-#pragma unroll
-            for (int v = 0; v < V; v++) fbar[j][v] = fma(wt, Fv[v], fbar[j][v]);
-        }
+        for (int t = 0; t < n; t++) qbar[v] = fma(B->w[t], fma(-a.sigma, acc[t][v], Qn[v]), qbar[v]);
     }
     if constexpr (Pde::kNCP) {
         // average of the non-conservative product: sum_a w_a g h_a D_j eta_a
@@ -579,7 +580,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         for (int t = 0; t < n; t++) {
             double qt[V];
 #pragma unroll
-            for (int v = 0; v < V; v++) qt[v] = fma(-a.dt, acc[t][v], Qn[v]);
+            for (int v = 0; v < V; v++) qt[v] = fma(-a.sigma, acc[t][v], Qn[v]);
             if (slot) {
 #pragma unroll
                 for (int j = 0; j < DIM; j++) eb[(cb * DIM + j) * S + s] = active ? Pde::ncp_input(qt) : 0.0;
@@ -610,15 +611,19 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
 
 #pragma unroll 1
     for (int j = 0; j < DIM; j++) {
+        // fbar_j = sum_a w_a F_j(q_a) from the final iterate q_a = Qn - dt acc[a]
         double fbj[V];
 #pragma unroll
-        for (int v = 0; v < V; v++) fbj[v] = fbar[0][v];
+        for (int v = 0; v < V; v++) fbj[v] = 0.0;
 #pragma unroll
-        for (int jj = 1; jj < DIM; jj++)
-            if (jj == j) {
+        for (int t = 0; t < n; t++) {
+            double qt[V], Fv[V];
 #pragma unroll
-                for (int v = 0; v < V; v++) fbj[v] = fbar[jj][v];
-            }
+            for (int v = 0; v < V; v++) qt[v] = fma(-a.sigma, acc[t][v], Qn[v]);
+            Pde::flux(coef, qt, j, Fv);
+#pragma unroll
+            for (int v = 0; v < V; v++) fbj[v] = fma(B->w[t], Fv[v], fbj[v]);
+        }
         if (slot) {
 #pragma unroll
             for (int v = 0; v < V; v++) FB[(cb * V + v) * S + s] = active ? fbj[v] : 0.0;
