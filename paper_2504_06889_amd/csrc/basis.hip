@@ -200,11 +200,15 @@ bool build_basis(int n, DevBasis &B) {
         for (int l = 0; l < n; l++) K1[k * n + l] = B.F1[k] * B.F1[l] - G[k][l];
     }
     if (!lu_solve(n, K1.data(), W.data(), A.data())) return false;
-    for (int k = 0; k < n; k++)
+    for (int k = 0; k < n; k++) {
+        double rs = 0.0;
         for (int l = 0; l < n; l++) {
             B.Atau[k][l] = A[k * n + l];
             B.Kxi[k][l] = G[k][l] / w[k];
+            rs += A[k * n + l];
         }
+        B.Arow[k] = rs;
+    }
     for (int p = 0; p < 4; p++)
         for (int i = 0; i < n; i++) {
             B.F0p[p][i] = round_prec(p, B.F0[i]);

@@ -92,105 +92,111 @@ __device__ __forceinline__ void lines_fp64(double *X, int nblk, const double (*M
 }
 
 // ---------------------------------------------------------------------------
-// Matrix-core line pass: Y = M along each line, inputs in format P (FP32,
-// BF16 or FP16), FP32 accumulation.  Each 16x16 MFMA tile holds LPR lines per
-// row: the row's K entries are LPR line segments of NB values, and the B
-// operand is the block-diagonal matrix diag(M^T, ..., M^T) (LPR blocks of
-// NB x NB, zero padded beyond n).  One tile thus differentiates 16*LPR lines.
-// Lane layouts (16x16xK, 64 lanes): A[row = lane%16][k = kw*(lane/16) + e],
-// B[k = kw*(lane/16) + e][col = lane%16], C[row = 4*(lane/16) + e][col = lane%16].
+// Matrix-core line contraction Y = M along every line of a block, inputs in
+// format P (FP32, BF16 or FP16), FP32 accumulation.  Input: line-major,
+// zero-padded X[line][NB] (NB = 8, or 4 when n <= 4).  Output: line-major Y
+// with padded stride OSTRIDE.  A 16x16 tile holds LPR = 16/NB lines per row;
+// the B operand is the constant block-diagonal diag(M^T, ..., M^T), so one
+// tile contracts 16*LPR lines.  Lane layouts (64 lanes, 16x16xK):
+// A[row = lane%16][k = 4*(lane/16) + e], B[k][col = lane%16],
+// C[row = 4*(lane/16) + e][col = lane%16].  Every lane-dependent offset is
+// fixed at init(); run() issues the wave's tiles in batches (loads, then the
+// independent MFMAs, then the stores) so LDS and matrix-core latencies overlap.
+// Lanes whose output column is a padding position store to unused slots.
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short i16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 
-template <int P, int n, int S, int F, class DirOf>
-__device__ __forceinline__ void lines_mfma(const typename Store<P>::T *X, float *Y, int nblk,
-                                           const float (*M)[kMaxN], DirOf dir_of, int tid,
-                                           int nthreads) {
+template <int P, int n>
+struct MfmaLines {
     using T = typename Store<P>::T;
-    constexpr int NB = n <= 4 ? 4 : 8;   // line segment length in the tile
-    constexpr int LPR = 16 / NB;         // lines per tile row
-    constexpr int LPT = 16 * LPR;        // lines per tile
-    const int NL = nblk * F;
-    const int ntiles = (NL + LPT - 1) / LPT;
-    const int lane = tid & 63, wave = tid >> 6, nwave = nthreads >> 6;
-    const int r = lane & 15, g = lane >> 4;
+    static constexpr int NB = n <= 4 ? 4 : 8;
+    static constexpr int LPR = 16 / NB;
+    static constexpr int LPT = 16 * LPR;
+    static constexpr int OSTRIDE = NB + NB / 4;
+    static constexpr int OTILE = LPT * OSTRIDE;
+    using VT = typename std::conditional<P == PBF16, i16x4, f16x4>::type;
+    VT bvec;
+    float bm[4];
+    int aoff, aoffm[4], coff;
 
-    // B operand (constant): B[k][col] = M[col%NB][k%NB] on diagonal blocks
-    auto bval = [&](int k) -> float {
-        const int kb = k / NB, kk = k % NB, cb = r / NB, cc = r % NB;
-        return (kb == cb && kk < n && cc < n) ? M[cc][kk] : 0.0f;
-    };
-    // address of position p of line L (or -1)
-    auto addr = [&](int L, int p) -> int {
-        if (L >= NL || p >= n) return -1;
-        const int f = L % F, blk = L / F;
-        const int j = dir_of(blk);
-        const int st = j == 0 ? 1 : (j == 1 ? n : n * n);
-        return blk * S + line_start<n>(f, j) + p * st;
-    };
-
-    if constexpr (P == P32) {
-        float b[4];
+    __device__ void init(const float (*M)[kMaxN], int lane) {
+        const int r = lane & 15, g = lane >> 4;
+        auto bval = [&](int k) -> float {
+            const int kb = k / NB, kk = k % NB, cbk = r / NB, cc = r % NB;
+            return (kb == cbk && kk < n && cc < n) ? M[cc][kk] : 0.0f;
+        };
 #pragma unroll
-        for (int m = 0; m < 4; m++) b[m] = bval(4 * m + g);
-        for (int tile = wave; tile < ntiles; tile += nwave) {
-            const int L0 = tile * LPT;
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int m = 0; m < 4; m++) {
-                const int k = 4 * m + g;
-                const int ad = addr(L0 + LPR * r + k / NB, k % NB);
-                const float av = ad >= 0 ? X[ad] : 0.0f;
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[m], acc, 0, 0, 0);
-            }
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int ad = addr(L0 + LPR * (4 * g + e) + r / NB, r % NB);
-                if (ad >= 0) Y[ad] = acc[e];
-            }
+        for (int m = 0; m < 4; m++) {
+            const int k = 4 * m + g;
+            bm[m] = bval(k);
+            aoffm[m] = (LPR * r + k / NB) * NB + k % NB;
         }
-    } else {
-        // 16x16x16 (bf16 / fp16): lane holds k = 4g .. 4g+3
-        T bb[4];
+        aoff = (LPR * r + (4 * g) / NB) * NB + (4 * g) % NB;
 #pragma unroll
-        for (int e = 0; e < 4; e++) bb[e] = round_to<P>(bval(4 * g + e));
-        for (int tile = wave; tile < ntiles; tile += nwave) {
-            const int L0 = tile * LPT;
-            T aa[4];
+        for (int e = 0; e < 4; e++) {
+            if constexpr (P == PBF16) bvec[e] = __builtin_bit_cast(short, round_to<PBF16>(bval(4 * g + e)));
+            else if constexpr (P == PF16) bvec[e] = round_to<PF16>(bval(4 * g + e));
+        }
+        coff = (LPR * 4 * g + r / NB) * OSTRIDE + r % NB;
+    }
+
+    template <int NTILE, int NWAVE>
+    __device__ void run(const T *X, float *Y, int wave) const {
+        constexpr int TPW = (NTILE + NWAVE - 1) / NWAVE;
+        constexpr int TB = TPW < 4 ? TPW : 4;
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int k = 4 * g + e;
-                const int ad = addr(L0 + LPR * r + k / NB, k % NB);
-                aa[e] = ad >= 0 ? X[ad] : round_to<P>(0.0f);
-            }
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            if constexpr (P == PBF16) {
-                i16x4 av, bv;
+        for (int k0 = 0; k0 < TPW; k0 += TB) {
+            f32x4 cc[TB];
+            if constexpr (P == P32) {
+                float av[TB][4];
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    av[e] = __builtin_bit_cast(short, aa[e]);
-                    bv[e] = __builtin_bit_cast(short, bb[e]);
+                for (int k = 0; k < TB; k++) {
+                    const int tile = wave + (k0 + k) * NWAVE;
+                    if (k0 + k < TPW && tile < NTILE) {
+#pragma unroll
+                        for (int m = 0; m < 4; m++) av[k][m] = X[tile * LPT * NB + aoffm[m]];
+                    }
                 }
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+#pragma unroll
+                for (int k = 0; k < TB; k++) {
+                    const int tile = wave + (k0 + k) * NWAVE;
+                    if (k0 + k < TPW && tile < NTILE) {
+                        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int m = 0; m < 4; m++) c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[k][m], bm[m], c, 0, 0, 0);
+                        cc[k] = c;
+                    }
+                }
             } else {
-                f16x4 av, bv;
+                VT av[TB];
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    av[e] = aa[e];
-                    bv[e] = bb[e];
+                for (int k = 0; k < TB; k++) {
+                    const int tile = wave + (k0 + k) * NWAVE;
+                    if (k0 + k < TPW && tile < NTILE) av[k] = *reinterpret_cast<const VT *>(X + tile * LPT * NB + aoff);
                 }
-                acc = __builtin_amdgcn_mfma_f32_16x16x16f16(av, bv, acc, 0, 0, 0);
+#pragma unroll
+                for (int k = 0; k < TB; k++) {
+                    const int tile = wave + (k0 + k) * NWAVE;
+                    if (k0 + k < TPW && tile < NTILE) {
+                        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+                        if constexpr (P == PBF16) cc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[k], bvec, z, 0, 0, 0);
+                        else cc[k] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[k], bvec, z, 0, 0, 0);
+                    }
+                }
             }
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int ad = addr(L0 + LPR * (4 * g + e) + r / NB, r % NB);
-                if (ad >= 0) Y[ad] = acc[e];
+            for (int k = 0; k < TB; k++) {
+                const int tile = wave + (k0 + k) * NWAVE;
+                if (k0 + k < TPW && tile < NTILE) {
+#pragma unroll
+                    for (int e = 0; e < 4; e++) Y[tile * OTILE + coff + LPR * OSTRIDE * e] = cc[k][e];
+                }
             }
         }
     }
-}
+};
 
 // ---------------------------------------------------------------------------
 // Picard line buffers.  Lines are numbered ((cb*DIM + j)*NV + v)*F + f: block
@@ -230,6 +236,30 @@ struct PicardLayout {
 };
 
 // ---------------------------------------------------------------------------
+// Epilogue line buffers (face projection and volume integral), one direction
+// at a time.  Input: position-major FP64 Ein[k][line] for the lines
+// (cell, q|f, var, face node), odd pitch.  Volume output: FP64 Evol[i][line]
+// for the lines (cell, var, face node), or, for a lower volume format, the
+// matrix-core operands (line-major input sized for FP32, FP32 output).
+// ---------------------------------------------------------------------------
+template <class Pde, int DIM, int N>
+struct EpiLayout {
+    using Sh = Shape<DIM, N>;
+    static constexpr int n = Sh::n, F = Sh::F, CPB = Sh::CPB, V = Pde::V;
+    static constexpr int NLV = CPB * V * F;
+    static constexpr int NLE = 2 * NLV;
+    static constexpr int NLPE = NLE | 1, NLPV = NLV | 1;
+    static constexpr size_t in_bytes = (size_t)n * NLPE * 8;
+    using ML = MfmaLines<P32, n>;  // tile geometry is the same for every format
+    static constexpr int NTILE = (NLV + ML::LPT - 1) / ML::LPT;
+    static constexpr size_t mfma_in = (size_t)NTILE * ML::LPT * ML::NB * 4;
+    static constexpr size_t mfma_out = (size_t)NTILE * ML::OTILE * 4;
+    static constexpr size_t vol64 = (size_t)n * NLPV * 8;
+    static constexpr size_t vol_bytes = vol64 > mfma_in + mfma_out ? vol64 : mfma_in + mfma_out;
+    static constexpr size_t bytes = in_bytes + vol_bytes;
+};
+
+// ---------------------------------------------------------------------------
 // LDS budget of the predictor
 // ---------------------------------------------------------------------------
 template <class Pde, int DIM, int N, int PP>
@@ -239,8 +269,7 @@ struct PredLds {
     static constexpr int NV = Pde::kNCP ? V + 1 : V;
     static constexpr int CPB = Sh::CPB, S = Sh::S;
     static constexpr size_t picard = PicardLayout<Pde, DIM, N, PP>::bytes;
-    // epilogue: qbar, fbar_j (double), volume staging (4-byte input + float output)
-    static constexpr size_t epi = (size_t)CPB * V * S * (8 + 8 + 4 + 4);
+    static constexpr size_t epi = EpiLayout<Pde, DIM, N>::bytes;
     static constexpr size_t ncp = Pde::kNCP ? (size_t)CPB * DIM * S * 8 : 0;
     static constexpr size_t bytes0 = picard > epi ? picard : epi;
     static constexpr size_t bytes = bytes0 > ncp ? bytes0 : ncp;
@@ -255,59 +284,28 @@ struct PredOcc {
         (PP != P64 && PredLds<Pde, DIM, N, PP>::bytes * 2 <= 160 * 1024 && Shape<DIM, N>::TPB <= 256) ? 2 : 1;
 };
 
-// Volume contribution along direction j in a lower format PV: round fbar_j,
-// matrix-core line pass with Kxi, accumulate into vol (FP64).
-template <class Pde, int DIM, int N, int PV>
-__device__ __forceinline__ void volume_dir_mixed(char *stage, const double *fbj_reg, double *vol,
-                                                 int j, int cb, int s, bool slot, bool active,
-                                                 const DevBasis *B, int tid) {
-    using Sh = Shape<DIM, N>;
-    constexpr int n = Sh::n, S = Sh::S, F = Sh::F, CPB = Sh::CPB, TPB = Sh::TPB, V = Pde::V;
-    using T = typename Store<PV>::T;
-    T *in = reinterpret_cast<T *>(stage);
-    float *out = reinterpret_cast<float *>(stage + (size_t)CPB * V * S * 4);
-    if (slot) {
-#pragma unroll
-        for (int v = 0; v < V; v++) in[(cb * V + v) * S + s] = round_to<PV>(active ? (float)fbj_reg[v] : 0.0f);
-    }
-    __syncthreads();
-    lines_mfma<PV, n, S, F>(in, out, CPB * V, B->Kxip[PV], [j](int) { return j; }, tid, TPB);
-    __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int v = 0; v < V; v++) vol[v] += (double)out[(cb * V + v) * S + s];
-    }
-}
-
-// Store one projected face value in the FLUX format.
-template <int FP>
-__device__ __forceinline__ void face_store(void *faces, long idx, double val) {
-    using T = typename FaceT<FP>::T;
-    reinterpret_cast<T *>(faces)[idx] = round_to<FP>((float)val);
-}
-template <>
-__device__ __forceinline__ void face_store<P64>(void *faces, long idx, double val) {
-    reinterpret_cast<double *>(faces)[idx] = val;
-}
-
-// Projection of one line onto a face (Alg. 1 "expansion"): FP64 or inputs
-// rounded to FP and FP32 accumulation.
+// Projection of one line onto the face at side 0 (xi = 0) or 1 (xi = 1), as in
+// Alg. 1 "expansion": FP64, or inputs rounded to the FLUX format FP and FP32
+// accumulation; stored in the FLUX format.
 template <int FP, int n>
-__device__ __forceinline__ double face_project(const double *src, int st, const DevBasis *B, int side) {
+__device__ __forceinline__ void project_store(void *faces, long idx, const double *x, const DevBasis *B,
+                                              int side) {
     if constexpr (FP == P64) {
         const double *E = side ? B->F1 : B->F0;
         double y = 0.0;
 #pragma unroll
-        for (int k = 0; k < n; k++) y = fma(E[k], src[k * st], y);
-        return y;
+        for (int k = 0; k < n; k++) y = fma(E[k], x[k], y);
+        reinterpret_cast<double *>(faces)[idx] = y;
     } else {
         const float *E = side ? B->F1p[FP] : B->F0p[FP];
         float y = 0.0f;
 #pragma unroll
-        for (int k = 0; k < n; k++) y += E[k] * widen(round_to<FP>((float)src[k * st]));
-        return (double)y;
+        for (int k = 0; k < n; k++) y += E[k] * widen(round_to<FP>((float)x[k]));
+        reinterpret_cast<typename FaceT<FP>::T *>(faces)[idx] = round_to<FP>(y);
     }
 }
+
+template <int P> struct PrecC { static constexpr int value = P; };
 
 // ---------------------------------------------------------------------------
 // Predictor + face projection + volume integral (Alg. 1, first traversal)
@@ -374,6 +372,9 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 for (int v = 0; v < V; v++) acc[t][v] = 0.0;
 #pragma unroll
             for (int b = 0; b < n; b++) {
+                // First iteration: every slice equals Qn, so slice 0's divergence
+                // serves all slices (acc_a = sum_b Atau[a][b] r, done below).
+                if (it == 0 && b > 0) continue;
                 // Padding cells (beyond ncell) hold Qn = 1 and never update it, so
                 // their fluxes are finite: no stale or non-finite bits enter the lines.
                 if (slot) {
@@ -410,9 +411,22 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                         if constexpr (Pde::kNCP) {
                             if (v >= 1 && v <= DIM) r += coef.g * q[b][0] * Xout[po[v - 1] + V * PL::VSTRIDE];
                         }
-                        if (v == 0 && src_here) r -= a.h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
+                        if (it == 0) {
 #pragma unroll
-                        for (int t = 0; t < n; t++) acc[t][v] = fma(B->Atau[t][b], r, acc[t][v]);
+                            for (int t = 0; t < n; t++) acc[t][v] = B->Arow[t] * r;
+                            if (v == 0 && src_here) {
+#pragma unroll
+                                for (int bb = 0; bb < n; bb++) {
+                                    const double sb = a.h * ricker(a.t + B->xi[bb] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
+#pragma unroll
+                                    for (int t = 0; t < n; t++) acc[t][0] = fma(B->Atau[t][bb], -sb, acc[t][0]);
+                                }
+                            }
+                        } else {
+                            if (v == 0 && src_here) r -= a.h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
+#pragma unroll
+                            for (int t = 0; t < n; t++) acc[t][v] = fma(B->Atau[t][b], r, acc[t][v]);
+                        }
                     }
                 }
             }
@@ -430,32 +444,8 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         for (int i = tid; i < PL::NLT * NB; i += TPB) Fb[i] = round_to<PP>(0.0f);
         const int lane = tid & 63, wave = tid >> 6;
         constexpr int NWAVE = TPB / 64;
-        const int r = lane & 15, g = lane >> 4;
-        // lane-constant operand offsets inside a tile (elements)
-        // output offset in the skewed FP32 layout (lane groups g land on different banks)
-        const int coff_o = PL::oelem(LPR * 4 * g + r / NB, r % NB);
-        // B operand: block-diagonal D^T, B[k][col] = D[col % NB][k % NB] on diagonal blocks
-        auto bval = [&](int k) -> float {
-            const int kb = k / NB, kk = k % NB, cbk = r / NB, cc = r % NB;
-            return (kb == cbk && kk < n && cc < n) ? B->Dp[PP][cc][kk] : 0.0f;
-        };
-        // constant B operands and lane offsets, set up once
-        float bm[4];      // FP32 path: B[4m+g][r]
-        int aoffm[4];     // FP32 path: A offsets of the four K=4 steps
-#pragma unroll
-        for (int m = 0; m < 4; m++) {
-            const int k = 4 * m + g;
-            bm[m] = bval(k);
-            aoffm[m] = (LPR * r + k / NB) * NB + k % NB;
-        }
-        const int aoff = (LPR * r + (4 * g) / NB) * NB + (4 * g) % NB;  // 16-bit paths
-        typename std::conditional<PP == PBF16, i16x4, f16x4>::type bvec;
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const T be = round_to<PP>(bval(4 * g + e));
-            if constexpr (PP == PBF16) bvec[e] = __builtin_bit_cast(short, be);
-            else if constexpr (PP == PF16) bvec[e] = be;
-        }
+        MfmaLines<PP, n> ml;
+        ml.init(B->Dp[PP], lane);
         float qf[n][V];
 #pragma unroll
         for (int t = 0; t < n; t++)
@@ -469,6 +459,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 for (int v = 0; v < V; v++) acc[t][v] = 0.0;
 #pragma unroll
             for (int b = 0; b < n; b++) {
+                if (it == 0 && b > 0) continue;  // first iteration: all slices equal Qn
                 const float *qb = qf[b];
                 // padding cells: finite fluxes of Qn = 1 (see the FP64 branch)
                 if (slot) {
@@ -482,56 +473,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                     }
                 }
                 __syncthreads();
-                if constexpr (PP == P32) {
-                    for (int tile = wave; tile < PL::NTILE; tile += NWAVE) {
-                        const int base = tile * LPT * NB;
-                        const int obase = tile * PL::OTILE;
-                        f32x4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                        for (int m = 0; m < 4; m++)
-                            c = __builtin_amdgcn_mfma_f32_16x16x4f32(Fb[base + aoffm[m]], bm[m], c, 0, 0, 0);
-#pragma unroll
-                        for (int e = 0; e < 4; e++) Rb[obase + coff_o + LPR * PL::OSTRIDE * e] = c[e];
-                    }
-                } else {
-                    // tiles of this wave in batches of TB: all operand loads, then the
-                    // independent MFMAs, then the stores, so that LDS and matrix-core
-                    // latencies overlap
-                    constexpr int TPW = (PL::NTILE + NWAVE - 1) / NWAVE;
-                    constexpr int TB = TPW < 4 ? TPW : 4;
-#pragma unroll
-                    for (int k0 = 0; k0 < TPW; k0 += TB) {
-                        using VT = typename std::conditional<PP == PBF16, i16x4, f16x4>::type;
-                        VT av[TB];
-                        f32x4 cc[TB];
-#pragma unroll
-                        for (int k = 0; k < TB; k++) {
-                            const int tile = wave + (k0 + k) * NWAVE;
-                            if (k0 + k < TPW && tile < PL::NTILE)
-                                av[k] = *reinterpret_cast<const VT *>(Fb + tile * LPT * NB + aoff);
-                        }
-#pragma unroll
-                        for (int k = 0; k < TB; k++) {
-                            const int tile = wave + (k0 + k) * NWAVE;
-                            if (k0 + k < TPW && tile < PL::NTILE) {
-                                f32x4 z = {0.f, 0.f, 0.f, 0.f};
-                                if constexpr (PP == PBF16)
-                                    cc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[k], bvec, z, 0, 0, 0);
-                                else
-                                    cc[k] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[k], bvec, z, 0, 0, 0);
-                            }
-                        }
-#pragma unroll
-                        for (int k = 0; k < TB; k++) {
-                            const int tile = wave + (k0 + k) * NWAVE;
-                            if (k0 + k < TPW && tile < PL::NTILE) {  // padding lanes store to unused slots
-                                const int obase = tile * PL::OTILE;
-#pragma unroll
-                                for (int e = 0; e < 4; e++) Rb[obase + coff_o + LPR * PL::OSTRIDE * e] = cc[k][e];
-                            }
-                        }
-                    }
-                }
+                ml.template run<PL::NTILE, NWAVE>(Fb, Rb, wave);
                 __syncthreads();
                 if (active) {
                     // R_b[v] = (1/h) sum_j (D_j F_j)[v] (- source), folded straight into
@@ -548,10 +490,23 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                             if (v >= 1 && v <= DIM)
                                 rr += (double)((float)coef.g * qb[0] * Rb[pr[v - 1] + V * PL::OVSTRIDE]);
                         }
-                        if (v == 0 && src_here)
-                            rr -= a.h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
+                        if (it == 0) {
 #pragma unroll
-                        for (int t = 0; t < n; t++) acc[t][v] = fma(B->Atau[t][b], rr, acc[t][v]);
+                            for (int t = 0; t < n; t++) acc[t][v] = B->Arow[t] * rr;
+                            if (v == 0 && src_here) {
+#pragma unroll
+                                for (int bb = 0; bb < n; bb++) {
+                                    const double sb = a.h * ricker(a.t + B->xi[bb] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
+#pragma unroll
+                                    for (int t = 0; t < n; t++) acc[t][0] = fma(B->Atau[t][bb], -sb, acc[t][0]);
+                                }
+                            }
+                        } else {
+                            if (v == 0 && src_here)
+                                rr -= a.h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
+#pragma unroll
+                            for (int t = 0; t < n; t++) acc[t][v] = fma(B->Atau[t][b], rr, acc[t][v]);
+                        }
                     }
                 }
             }
@@ -598,84 +553,137 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     }
 
     // ---------------- face projection and volume integral ----------------
-    double *QB = reinterpret_cast<double *>(smem);              // [CPB][V][S]
-    double *FB = QB + (size_t)CPB * V * S;                      // [CPB][V][S]
-    char *stage = reinterpret_cast<char *>(FB + (size_t)CPB * V * S);
-    if (slot) {
-#pragma unroll
-        for (int v = 0; v < V; v++) QB[(cb * V + v) * S + s] = active ? qbar[v] : 0.0;
+    // Per direction j: the owners write qbar and fbar_j at their position on
+    // the lines along j; one thread per (cell, var, face node) projects both
+    // lines onto the two faces (Alg. 1 "expansion") and, for an FP64 volume,
+    // applies Kxi along the fbar_j line; a lower volume format runs the same
+    // contraction on the matrix cores.  The owners then gather their node's
+    // volume term.  Two barriers per direction: the line pass reads Ein and
+    // writes the volume buffer, which the owners only read after the second
+    // barrier and only overwrite (Ein) after it.
+    using EL = EpiLayout<Pde, DIM, N>;
+    double *Ein = reinterpret_cast<double *>(smem);                  // [n][NLPE]
+    double *Evol = reinterpret_cast<double *>(smem + EL::in_bytes);  // [n][NLPV]
+    char *Mx = smem + EL::in_bytes;                                   // matrix-core input
+    float *My = reinterpret_cast<float *>(smem + EL::in_bytes + EL::mfma_in);
+    const int vp = a.vol_prec;
+    if (vp != P64) {
+        // zero padding of the line-major operands (positions >= n, lines >= NLV);
+        // the owners never write these slots, so no barrier is needed here
+        constexpr int NB = EL::ML::NB;
+        const int esz = vp == P32 ? 4 : 2;
+        for (int idx = tid; idx < EL::NTILE * EL::ML::LPT * NB; idx += TPB) {
+            if (idx % NB >= n || idx / NB >= EL::NLV) {
+                if (esz == 4) reinterpret_cast<float *>(Mx)[idx] = 0.0f;
+                else reinterpret_cast<unsigned short *>(Mx)[idx] = 0;
+            }
+        }
     }
     double vol[V];
 #pragma unroll
     for (int v = 0; v < V; v++) vol[v] = 0.0;
+    const int lane = tid & 63, wave = tid >> 6;
+    constexpr int NWAVE = TPB / 64;
 
 #pragma unroll 1
     for (int j = 0; j < DIM; j++) {
-        // fbar_j = sum_a w_a F_j(q_a) from the final iterate q_a = Qn - dt acc[a]
+        // fbar_j = sum_a w_a F_j(q_a); for a linear flux this is F_j(qbar)
         double fbj[V];
+        if constexpr (Pde::kLinear) {
+            Pde::flux(coef, qbar, j, fbj);
+        } else {
 #pragma unroll
-        for (int v = 0; v < V; v++) fbj[v] = 0.0;
+            for (int v = 0; v < V; v++) fbj[v] = 0.0;
 #pragma unroll
-        for (int t = 0; t < n; t++) {
-            double qt[V], Fv[V];
+            for (int t = 0; t < n; t++) {
+                double qt[V], Fv[V];
 #pragma unroll
-            for (int v = 0; v < V; v++) qt[v] = fma(-a.sigma, acc[t][v], Qn[v]);
-            Pde::flux(coef, qt, j, Fv);
+                for (int v = 0; v < V; v++) qt[v] = fma(-a.sigma, acc[t][v], Qn[v]);
+                Pde::flux(coef, qt, j, Fv);
 #pragma unroll
-            for (int v = 0; v < V; v++) fbj[v] = fma(B->w[t], Fv[v], fbj[v]);
+                for (int v = 0; v < V; v++) fbj[v] = fma(B->w[t], Fv[v], fbj[v]);
+            }
         }
+        const int ij = coord<n>(s, j), fj = face_of<n, DIM>(s, j);
         if (slot) {
 #pragma unroll
-            for (int v = 0; v < V; v++) FB[(cb * V + v) * S + s] = active ? fbj[v] : 0.0;
-        }
-        __syncthreads();
-        // faces of direction j: items (cb, side, q|f, v, f)
-        {
-            const int st = j == 0 ? 1 : (j == 1 ? n : n * n);
-            constexpr int NFI = CPB * 2 * 2 * V * F;
-            for (int itm = tid; itm < NFI; itm += TPB) {
-                const int f = itm % F;
-                int rr = itm / F;
-                const int v = rr % V;
-                rr /= V;
-                const int qf = rr % 2;
-                rr /= 2;
-                const int side = rr % 2;
-                const int cbi = rr / 2;
-                const long c = cell0 + cbi;
-                if (c >= a.ncell) continue;
-                const double *src = (qf == 0 ? QB : FB) + (cbi * V + v) * S + line_start<n>(f, j);
-                const long idx = ((((c * DIM + j) * 2 + side) * 2 + qf) * V + v) * (long)F + f;
-                switch (a.flux_prec) {
-                case P64: face_store<P64>(a.faces, idx, face_project<P64, n>(src, st, B, side)); break;
-                case P32: face_store<P32>(a.faces, idx, face_project<P32, n>(src, st, B, side)); break;
-                case PBF16: face_store<PBF16>(a.faces, idx, face_project<PBF16, n>(src, st, B, side)); break;
-                default: face_store<PF16>(a.faces, idx, face_project<PF16, n>(src, st, B, side)); break;
-                }
+            for (int v = 0; v < V; v++) {
+                Ein[ij * EL::NLPE + ((cb * 2 + 0) * V + v) * F + fj] = active ? qbar[v] : 0.0;
+                Ein[ij * EL::NLPE + ((cb * 2 + 1) * V + v) * F + fj] = active ? fbj[v] : 0.0;
             }
-        }
-        // volume along j
-        if (a.vol_prec == P64) {
-            if (active) {
-                const int i = coord<n>(s, j);
-                const int st = j == 0 ? 1 : (j == 1 ? n : n * n);
+            if (vp != P64) {
+                const int l0 = (cb * V) * F + fj;
 #pragma unroll
                 for (int v = 0; v < V; v++) {
-                    const double *line = FB + (cb * V + v) * S + (s - i * st);
-                    double y = 0.0;
-#pragma unroll
-                    for (int k = 0; k < n; k++) y = fma(B->Kxi[i][k], line[k * st], y);
-                    vol[v] += y;
+                    const float x = active ? (float)fbj[v] : 0.0f;
+                    const int e = (l0 + v * F) * EL::ML::NB + ij;
+                    if (vp == P32) reinterpret_cast<float *>(Mx)[e] = x;
+                    else if (vp == PBF16) reinterpret_cast<__hip_bfloat16 *>(Mx)[e] = round_to<PBF16>(x);
+                    else reinterpret_cast<_Float16 *>(Mx)[e] = round_to<PF16>(x);
                 }
             }
-        } else if (a.vol_prec == P32) {
-            volume_dir_mixed<Pde, DIM, N, P32>(stage, fbj, vol, j, cb, s, slot, active, B, tid);
-        } else if (a.vol_prec == PBF16) {
-            volume_dir_mixed<Pde, DIM, N, PBF16>(stage, fbj, vol, j, cb, s, slot, active, B, tid);
-        } else {
-            volume_dir_mixed<Pde, DIM, N, PF16>(stage, fbj, vol, j, cb, s, slot, active, B, tid);
         }
         __syncthreads();
+        if (vp == P32) {
+            MfmaLines<P32, n> ml;
+            ml.init(B->Kxip[P32], lane);
+            ml.template run<EL::NTILE, NWAVE>(reinterpret_cast<const float *>(Mx), My, wave);
+        } else if (vp == PBF16) {
+            MfmaLines<PBF16, n> ml;
+            ml.init(B->Kxip[PBF16], lane);
+            ml.template run<EL::NTILE, NWAVE>(reinterpret_cast<const __hip_bfloat16 *>(Mx), My, wave);
+        } else if (vp == PF16) {
+            MfmaLines<PF16, n> ml;
+            ml.init(B->Kxip[PF16], lane);
+            ml.template run<EL::NTILE, NWAVE>(reinterpret_cast<const _Float16 *>(Mx), My, wave);
+        }
+        auto line_pass = [&](auto fpc) {
+            constexpr int FP = decltype(fpc)::value;
+            for (int L = tid; L < EL::NLV; L += TPB) {
+                const int f = L % F, r = L / F, v = r % V, cbi = r / V;
+                const long c = cell0 + cbi;
+                double xq[n], xf[n];
+#pragma unroll
+                for (int k = 0; k < n; k++) {
+                    xq[k] = Ein[k * EL::NLPE + ((cbi * 2 + 0) * V + v) * F + f];
+                    xf[k] = Ein[k * EL::NLPE + ((cbi * 2 + 1) * V + v) * F + f];
+                }
+                if (c < a.ncell) {
+                    const long base = ((c * DIM + j) * 2) * 2 * V;
+#pragma unroll
+                    for (int side = 0; side < 2; side++) {
+                        project_store<FP, n>(a.faces, ((base + (side * 2 + 0) * V) + v) * (long)F + f, xq, B, side);
+                        project_store<FP, n>(a.faces, ((base + (side * 2 + 1) * V) + v) * (long)F + f, xf, B, side);
+                    }
+                }
+                if (vp == P64) {
+#pragma unroll
+                    for (int i = 0; i < n; i++) {
+                        double y = 0.0;
+#pragma unroll
+                        for (int k = 0; k < n; k++) y = fma(B->Kxi[i][k], xf[k], y);
+                        Evol[i * EL::NLPV + L] = y;
+                    }
+                }
+            }
+        };
+        switch (a.flux_prec) {
+        case P64: line_pass(PrecC<P64>{}); break;
+        case P32: line_pass(PrecC<P32>{}); break;
+        case PBF16: line_pass(PrecC<PBF16>{}); break;
+        default: line_pass(PrecC<PF16>{}); break;
+        }
+        __syncthreads();
+        if (active) {
+            const int l0 = (cb * V) * F + fj;
+            if (vp == P64) {
+#pragma unroll
+                for (int v = 0; v < V; v++) vol[v] += Evol[ij * EL::NLPV + l0 + v * F];
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; v++) vol[v] += (double)My[(l0 + v * F) * EL::ML::OSTRIDE + ij];
+            }
+        }
     }
 
     if (active && a.write_state) {
