@@ -203,7 +203,7 @@ struct MfmaLines {
 // cell cb, direction j, variable v (NV = V, plus eta for the non-conservative
 // term), face node f.
 //  FP64:  position-major X[k][line] with an odd pitch NLP (conflict-free
-//         column access by consecutive lines), separate input and output.
+//         column access by consecutive lines), differentiated in place.
 //  other: line-major F[line][NB] (NB = 4 or 8 positions, zero padded) in the
 //         contraction format, so that a lane's 4 MFMA operand values are one
 //         8-byte load; FP32 results in the same layout.
@@ -232,7 +232,7 @@ struct PicardLayout {
     __device__ static constexpr int oelem(int line, int k) { return line * OSTRIDE + k; }
     static constexpr size_t obytes = (size_t)NTILE * OTILE * 4;
     static constexpr size_t bytes =
-        PP == P64 ? (size_t)2 * n * NLP * 8 : (size_t)NLT * NB * sizeof(typename Store<PP>::T) + obytes;
+        PP == P64 ? (size_t)n * NLP * 8 : (size_t)NLT * NB * sizeof(typename Store<PP>::T) + obytes;
 };
 
 // ---------------------------------------------------------------------------
@@ -332,22 +332,31 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     double Qn[V];
 #pragma unroll
     for (int v = 0; v < V; v++) Qn[v] = active ? a.Q[(cell * V + v) * S + s] : 1.0;
-    // The final Picard iterate is q_a = Qn - (dt/h) acc[a] (acc of the last
-    // iteration accumulates Atau applied to h R_b); the epilogue evaluates it
-    // on the fly from acc.
 
     const bool src_here = active && cell == a.src_cell;
     const double src_phi = src_here ? a.src_phi[s] : 0.0;
     const int iters = a.iters;
 
     // ---------------- Picard iterations (eq. Picard) ----------------
-    // Per slice b: the node owners write F_j(q_b) into the line buffer, every
+    // z[t] holds the FP64 iterate q_t at this node.  Within an iteration,
+    // slice b's divergence only needs q_b, so once it is evaluated row b is
+    // reused for h R_b (the 1/h of R_b is folded into sigma = dt/h); after the
+    // last slice every row is replaced by q_a = Qn - sigma sum_b Atau[a][b] h R_b.
+    // Per slice: the node owners write F_j(q_b) into the line buffer, every
     // line is differentiated, and the owners gather sum_j D_j F_j at their
-    // node and fold it into acc[a] += Atau[a][b] R_b.  Two barriers per slice:
-    // the line pass reads a buffer the owners do not touch until the next
-    // slice's first barrier, and writes one they only read after the second.
+    // node.  Each owner reads and writes only its own slots of the buffer,
+    // which the line pass touches only between the two barriers, so two
+    // barriers per slice suffice.
+    // First iteration: every slice equals Qn, so slice 0's divergence serves
+    // all of them: q_a = Qn - sigma (sum_b Atau[a][b]) h R_0 (+ source terms).
+    // Padding cells (beyond ncell) hold Qn = 1 and never update it, so their
+    // fluxes are finite: no stale or non-finite bits enter the lines.
     using PL = PicardLayout<Pde, DIM, N, PP>;
-    double acc[n][V];
+    double z[n][V];
+#pragma unroll
+    for (int t = 0; t < n; t++)
+#pragma unroll
+        for (int v = 0; v < V; v++) z[t][v] = Qn[v];
     // per-thread offset of its node in each direction's lines (variable 0)
     int po[DIM], pr[DIM];
 #pragma unroll
@@ -356,112 +365,111 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         po[j] = PL::elem(line0, coord<n>(s, j));
         pr[j] = PL::oelem(line0, coord<n>(s, j));
     }
+    // fold h R_b (variable v, slice b) into the iterate rows
+    auto fold = [&](int it, int b, int v, double r) {
+        if (it == 0) {
+#pragma unroll
+            for (int t = 0; t < n; t++) {
+                double acc = B->Arow[t] * r;
+                if (v == 0 && src_here) {
+#pragma unroll
+                    for (int bb = 0; bb < n; bb++) {
+                        const double sb = a.h * ricker(a.t + B->xi[bb] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
+                        acc = fma(B->Atau[t][bb], -sb, acc);
+                    }
+                }
+                z[t][v] = fma(-a.sigma, acc, Qn[v]);
+            }
+        } else {
+            if (v == 0 && src_here) r -= a.h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
+#pragma unroll
+            for (int bb = 0; bb < n; bb++)
+                if (bb == b) z[bb][v] = r;
+        }
+    };
+    // end of an iteration > 0: rows hold h R_b; replace them by the new iterate
+    auto update = [&]() {
+#pragma unroll
+        for (int v = 0; v < V; v++) {
+            double r[n];
+#pragma unroll
+            for (int b = 0; b < n; b++) r[b] = z[b][v];
+#pragma unroll
+            for (int t = 0; t < n; t++) {
+                double acc = 0.0;
+#pragma unroll
+                for (int b = 0; b < n; b++) acc = fma(B->Atau[t][b], r[b], acc);
+                z[t][v] = fma(-a.sigma, acc, Qn[v]);
+            }
+        }
+    };
     if constexpr (PP == P64) {
-        double *Xin = reinterpret_cast<double *>(smem);   // [n][NLP] position-major
-        double *Xout = Xin + n * PL::NLP;
-        double q[n][V];
-#pragma unroll
-        for (int t = 0; t < n; t++)
-#pragma unroll
-            for (int v = 0; v < V; v++) q[t][v] = Qn[v];
+        double *X = reinterpret_cast<double *>(smem);  // [n][NLP] position-major
 #pragma unroll 1
         for (int it = 0; it < iters; it++) {
 #pragma unroll
-            for (int t = 0; t < n; t++)
-#pragma unroll
-                for (int v = 0; v < V; v++) acc[t][v] = 0.0;
-#pragma unroll
             for (int b = 0; b < n; b++) {
-                // First iteration: every slice equals Qn, so slice 0's divergence
-                // serves all slices (acc_a = sum_b Atau[a][b] r, done below).
                 if (it == 0 && b > 0) continue;
-                // Padding cells (beyond ncell) hold Qn = 1 and never update it, so
-                // their fluxes are finite: no stale or non-finite bits enter the lines.
                 if (slot) {
 #pragma unroll
                     for (int j = 0; j < DIM; j++) {
                         double Fv[V];
-                        Pde::flux(coef, q[b], j, Fv);
+                        Pde::flux(coef, z[b], j, Fv);
 #pragma unroll
-                        for (int v = 0; v < V; v++) Xin[po[j] + v * PL::VSTRIDE] = Fv[v];
-                        if constexpr (Pde::kNCP) Xin[po[j] + V * PL::VSTRIDE] = Pde::ncp_input(q[b]);
+                        for (int v = 0; v < V; v++) X[po[j] + v * PL::VSTRIDE] = Fv[v];
+                        if constexpr (Pde::kNCP) X[po[j] + V * PL::VSTRIDE] = Pde::ncp_input(z[b]);
                     }
                 }
                 __syncthreads();
                 for (int Ln = tid; Ln < PL::NL; Ln += TPB) {
                     double x[n];
 #pragma unroll
-                    for (int k = 0; k < n; k++) x[k] = Xin[k * PL::NLP + Ln];
+                    for (int k = 0; k < n; k++) x[k] = X[k * PL::NLP + Ln];
 #pragma unroll
                     for (int i = 0; i < n; i++) {
                         double y = 0.0;
 #pragma unroll
                         for (int k = 0; k < n; k++) y = fma(B->D[i][k], x[k], y);
-                        Xout[i * PL::NLP + Ln] = y;
+                        X[i * PL::NLP + Ln] = y;
                     }
                 }
                 __syncthreads();
                 if (active) {
-                    // h R_b: the 1/h of R_b is folded into sigma = dt/h of the update
+                    // descending v: the non-conservative term of v >= 1 reads q_b[0]
 #pragma unroll
-                    for (int v = 0; v < V; v++) {
+                    for (int v = V - 1; v >= 0; v--) {
                         double r = 0.0;
 #pragma unroll
-                        for (int j = 0; j < DIM; j++) r += Xout[po[j] + v * PL::VSTRIDE];
+                        for (int j = 0; j < DIM; j++) r += X[po[j] + v * PL::VSTRIDE];
                         if constexpr (Pde::kNCP) {
-                            if (v >= 1 && v <= DIM) r += coef.g * q[b][0] * Xout[po[v - 1] + V * PL::VSTRIDE];
+                            if (v >= 1 && v <= DIM) r += coef.g * z[b][0] * X[po[v - 1] + V * PL::VSTRIDE];
                         }
-                        if (it == 0) {
-#pragma unroll
-                            for (int t = 0; t < n; t++) acc[t][v] = B->Arow[t] * r;
-                            if (v == 0 && src_here) {
-#pragma unroll
-                                for (int bb = 0; bb < n; bb++) {
-                                    const double sb = a.h * ricker(a.t + B->xi[bb] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
-#pragma unroll
-                                    for (int t = 0; t < n; t++) acc[t][0] = fma(B->Atau[t][bb], -sb, acc[t][0]);
-                                }
-                            }
-                        } else {
-                            if (v == 0 && src_here) r -= a.h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
-#pragma unroll
-                            for (int t = 0; t < n; t++) acc[t][v] = fma(B->Atau[t][b], r, acc[t][v]);
-                        }
+                        fold(it, b, v, r);
                     }
                 }
             }
-#pragma unroll
-            for (int t = 0; t < n; t++)
-#pragma unroll
-                for (int v = 0; v < V; v++) q[t][v] = fma(-a.sigma, acc[t][v], Qn[v]);
+            if (it > 0 && active) update();
         }
     } else {
         using T = typename Store<PP>::T;
-        constexpr int NB = PL::NB, LPR = PL::LPR, LPT = PL::LPT;
+        constexpr int NB = PL::NB;
         T *Fb = reinterpret_cast<T *>(smem);                                    // [NLT][NB] line-major
-        float *Rb = reinterpret_cast<float *>(smem + (size_t)PL::NLT * NB * sizeof(T));  // skewed [NLT][NB]
+        float *Rb = reinterpret_cast<float *>(smem + (size_t)PL::NLT * NB * sizeof(T));  // [NLT][OSTRIDE]
         // zero padding (positions >= n and lines >= NL are never written)
         for (int i = tid; i < PL::NLT * NB; i += TPB) Fb[i] = round_to<PP>(0.0f);
         const int lane = tid & 63, wave = tid >> 6;
         constexpr int NWAVE = TPB / 64;
         MfmaLines<PP, n> ml;
         ml.init(B->Dp[PP], lane);
-        float qf[n][V];
-#pragma unroll
-        for (int t = 0; t < n; t++)
-#pragma unroll
-            for (int v = 0; v < V; v++) qf[t][v] = (float)Qn[v];
 #pragma unroll 1
         for (int it = 0; it < iters; it++) {
 #pragma unroll
-            for (int t = 0; t < n; t++)
-#pragma unroll
-                for (int v = 0; v < V; v++) acc[t][v] = 0.0;
-#pragma unroll
             for (int b = 0; b < n; b++) {
-                if (it == 0 && b > 0) continue;  // first iteration: all slices equal Qn
-                const float *qb = qf[b];
-                // padding cells: finite fluxes of Qn = 1 (see the FP64 branch)
+                if (it == 0 && b > 0) continue;
+                // the flux sees the FP32 rounding of the FP64 iterate
+                float qb[V];
+#pragma unroll
+                for (int v = 0; v < V; v++) qb[v] = (float)z[b][v];
                 if (slot) {
 #pragma unroll
                     for (int j = 0; j < DIM; j++) {
@@ -476,12 +484,10 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 ml.template run<PL::NTILE, NWAVE>(Fb, Rb, wave);
                 __syncthreads();
                 if (active) {
-                    // R_b[v] = (1/h) sum_j (D_j F_j)[v] (- source), folded straight into
-                    // acc[a][v] += Atau[a][b] R_b[v] one variable at a time
 #pragma unroll
-                    for (int v = 0; v < V; v++) {
+                    for (int v = V - 1; v >= 0; v--) {
                         // the divergence sum over directions is part of the FP32
-                        // contraction; h R_b is accumulated (1/h folded into sigma)
+                        // contraction
                         float rf = 0.0f;
 #pragma unroll
                         for (int j = 0; j < DIM; j++) rf += Rb[pr[j] + v * PL::OVSTRIDE];
@@ -490,30 +496,11 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                             if (v >= 1 && v <= DIM)
                                 rr += (double)((float)coef.g * qb[0] * Rb[pr[v - 1] + V * PL::OVSTRIDE]);
                         }
-                        if (it == 0) {
-#pragma unroll
-                            for (int t = 0; t < n; t++) acc[t][v] = B->Arow[t] * rr;
-                            if (v == 0 && src_here) {
-#pragma unroll
-                                for (int bb = 0; bb < n; bb++) {
-                                    const double sb = a.h * ricker(a.t + B->xi[bb] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
-#pragma unroll
-                                    for (int t = 0; t < n; t++) acc[t][0] = fma(B->Atau[t][bb], -sb, acc[t][0]);
-                                }
-                            }
-                        } else {
-                            if (v == 0 && src_here)
-                                rr -= a.h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
-#pragma unroll
-                            for (int t = 0; t < n; t++) acc[t][v] = fma(B->Atau[t][b], rr, acc[t][v]);
-                        }
+                        fold(it, b, v, rr);
                     }
                 }
             }
-#pragma unroll
-            for (int t = 0; t < n; t++)
-#pragma unroll
-                for (int v = 0; v < V; v++) qf[t][v] = (float)fma(-a.sigma, acc[t][v], Qn[v]);
+            if (it > 0 && active) update();
         }
     }
     __syncthreads();
@@ -526,7 +513,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         qbar[v] = 0.0;
         nbar[v] = 0.0;
 #pragma unroll
-        for (int t = 0; t < n; t++) qbar[v] = fma(B->w[t], fma(-a.sigma, acc[t][v], Qn[v]), qbar[v]);
+        for (int t = 0; t < n; t++) qbar[v] = fma(B->w[t], z[t][v], qbar[v]);
     }
     if constexpr (Pde::kNCP) {
         // average of the non-conservative product: sum_a w_a g h_a D_j eta_a
@@ -535,7 +522,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         for (int t = 0; t < n; t++) {
             double qt[V];
 #pragma unroll
-            for (int v = 0; v < V; v++) qt[v] = fma(-a.sigma, acc[t][v], Qn[v]);
+            for (int v = 0; v < V; v++) qt[v] = z[t][v];
             if (slot) {
 #pragma unroll
                 for (int j = 0; j < DIM; j++) eb[(cb * DIM + j) * S + s] = active ? Pde::ncp_input(qt) : 0.0;
@@ -598,7 +585,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
             for (int t = 0; t < n; t++) {
                 double qt[V], Fv[V];
 #pragma unroll
-                for (int v = 0; v < V; v++) qt[v] = fma(-a.sigma, acc[t][v], Qn[v]);
+                for (int v = 0; v < V; v++) qt[v] = z[t][v];
                 Pde::flux(coef, qt, j, Fv);
 #pragma unroll
                 for (int v = 0; v < V; v++) fbj[v] = fma(B->w[t], Fv[v], fbj[v]);
