@@ -47,6 +47,10 @@ struct DevBasis {
     float F0p[4][kMaxN], F1p[4][kMaxN], L0p[4][kMaxN], L1p[4][kMaxN];
 };
 
+// Kernels read the basis through the constant address space: it does not
+// change during a launch, so uniform reads become scalar loads.
+using CBasis = const __attribute__((address_space(4))) DevBasis;
+
 // ---------------------------------------------------------------------------
 // Precision conversions (round-to-nearest-even)
 // ---------------------------------------------------------------------------
@@ -205,6 +209,16 @@ struct Swe {  // (h, hu, hv, b); pressure term as non-conservative g h grad(h+b)
     template <class T>
     __device__ static T ncp_input(const T *q) { return q[0] + q[3]; }
 };
+
+// Flux in a direction j that is only known at run time (but uniform): one
+// branch per direction, so that the PDE sees a compile-time j and no
+// register array is indexed dynamically.
+template <class Pde, int DIM, class T, class C>
+__device__ __forceinline__ void flux_dir(const C &c, const T *q, int j, T *F) {
+    if (j == 0) Pde::flux(c, q, 0, F);
+    else if (DIM == 2 || j == 1) Pde::flux(c, q, 1, F);
+    else Pde::flux(c, q, 2, F);
+}
 
 // ---------------------------------------------------------------------------
 // Node index helpers (node = i0 + n i1 + n^2 i2)

@@ -69,8 +69,8 @@ __device__ __forceinline__ long neighbour(long cell, int j, int dir, const int *
 // face node through which the line runs; the direction of block blk is
 // dir_of(blk).
 // ---------------------------------------------------------------------------
-template <int n, int S, int F, class DirOf>
-__device__ __forceinline__ void lines_fp64(double *X, int nblk, const double (*M)[kMaxN], DirOf dir_of,
+template <int n, int S, int F, class MT, class DirOf>
+__device__ __forceinline__ void lines_fp64(double *X, int nblk, MT M, DirOf dir_of,
                                            int tid, int nthreads) {
     const int NL = nblk * F;
     for (int L = tid; L < NL; L += nthreads) {
@@ -121,7 +121,8 @@ struct MfmaLines {
     float bm[4];
     int aoff, aoffm[4], coff;
 
-    __device__ void init(const float (*M)[kMaxN], int lane) {
+    template <class MT>
+    __device__ void init(MT M, int lane) {
         const int r = lane & 15, g = lane >> 4;
         auto bval = [&](int k) -> float {
             const int kb = k / NB, kk = k % NB, cbk = r / NB, cc = r % NB;
@@ -275,32 +276,28 @@ struct PredLds {
     static constexpr size_t bytes = bytes0 > ncp ? bytes0 : ncp;
 };
 
-// Target occupancy of the predictor: the lower-precision paths keep the
-// Picard iterate in FP32 registers and can run two wavefronts per SIMD when
-// their LDS allows two workgroups per CU.
+// Target occupancy of the predictor: two wavefronts per SIMD (at most 256
+// registers per lane) whenever the LDS allows two workgroups per CU.
 template <class Pde, int DIM, int N, int PP>
 struct PredOcc {
     static constexpr int waves =
-        (PP != P64 && PredLds<Pde, DIM, N, PP>::bytes * 2 <= 160 * 1024 && Shape<DIM, N>::TPB <= 256) ? 2 : 1;
+        (PredLds<Pde, DIM, N, PP>::bytes * 2 <= 160 * 1024 && Shape<DIM, N>::TPB <= 256) ? 2 : 1;
 };
 
 // Projection of one line onto the face at side 0 (xi = 0) or 1 (xi = 1), as in
 // Alg. 1 "expansion": FP64, or inputs rounded to the FLUX format FP and FP32
 // accumulation; stored in the FLUX format.
 template <int FP, int n>
-__device__ __forceinline__ void project_store(void *faces, long idx, const double *x, const DevBasis *B,
-                                              int side) {
+__device__ __forceinline__ void project_store(void *faces, long idx, const double *x, CBasis *B, int side) {
     if constexpr (FP == P64) {
-        const double *E = side ? B->F1 : B->F0;
         double y = 0.0;
 #pragma unroll
-        for (int k = 0; k < n; k++) y = fma(E[k], x[k], y);
+        for (int k = 0; k < n; k++) y = fma(side ? B->F1[k] : B->F0[k], x[k], y);
         reinterpret_cast<double *>(faces)[idx] = y;
     } else {
-        const float *E = side ? B->F1p[FP] : B->F0p[FP];
         float y = 0.0f;
 #pragma unroll
-        for (int k = 0; k < n; k++) y += E[k] * widen(round_to<FP>((float)x[k]));
+        for (int k = 0; k < n; k++) y += (side ? B->F1p[FP][k] : B->F0p[FP][k]) * widen(round_to<FP>((float)x[k]));
         reinterpret_cast<typename FaceT<FP>::T *>(faces)[idx] = round_to<FP>(y);
     }
 }
@@ -319,7 +316,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     constexpr int V = Pde::V, NV = L::NV;
     __shared__ __attribute__((aligned(16))) char smem[L::bytes];
 
-    const DevBasis *B = a.B;
+    CBasis *B = (CBasis *)a.B;
     const int tid = threadIdx.x;
     const int cb = tid / S, s = tid % S;
     const long blk = xcd_block(blockIdx.x, gridDim.x);
@@ -352,11 +349,22 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     // Padding cells (beyond ncell) hold Qn = 1 and never update it, so their
     // fluxes are finite: no stale or non-finite bits enter the lines.
     using PL = PicardLayout<Pde, DIM, N, PP>;
-    double z[n][V];
+    // Lower-precision predictor of a linear system without non-conservative
+    // term: the iterate is only ever used rounded to FP32 (flux input) or
+    // through qbar (fbar = F(qbar)), and the FP32 divergence is exact in FP32,
+    // so the rows can be FP32 with qbar accumulated in FP64 as the last
+    // iterate is formed (same values as FP64 rows); the point source, an FP64
+    // term, is then applied when the rows are combined.
+    constexpr bool FR = PP != P64 && Pde::kLinear && !Pde::kNCP;
+    using RowT = typename std::conditional<FR, float, double>::type;
+    RowT z[n][V];
 #pragma unroll
     for (int t = 0; t < n; t++)
 #pragma unroll
-        for (int v = 0; v < V; v++) z[t][v] = Qn[v];
+        for (int v = 0; v < V; v++) z[t][v] = (RowT)Qn[v];
+    double qbar[V];
+#pragma unroll
+    for (int v = 0; v < V; v++) qbar[v] = 0.0;
     // per-thread offset of its node in each direction's lines (variable 0)
     int po[DIM], pr[DIM];
 #pragma unroll
@@ -365,41 +373,49 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         po[j] = PL::elem(line0, coord<n>(s, j));
         pr[j] = PL::oelem(line0, coord<n>(s, j));
     }
+    auto src_term = [&](int b) {
+        return a.h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
+    };
     // fold h R_b (variable v, slice b) into the iterate rows
     auto fold = [&](int it, int b, int v, double r) {
         if (it == 0) {
+            const bool last = iters == 1;
 #pragma unroll
             for (int t = 0; t < n; t++) {
                 double acc = B->Arow[t] * r;
                 if (v == 0 && src_here) {
 #pragma unroll
-                    for (int bb = 0; bb < n; bb++) {
-                        const double sb = a.h * ricker(a.t + B->xi[bb] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
-                        acc = fma(B->Atau[t][bb], -sb, acc);
-                    }
+                    for (int bb = 0; bb < n; bb++) acc = fma(B->Atau[t][bb], -src_term(bb), acc);
                 }
-                z[t][v] = fma(-a.sigma, acc, Qn[v]);
+                const double qt = fma(-a.sigma, acc, Qn[v]);
+                if (FR && last) qbar[v] = fma(B->w[t], qt, qbar[v]);
+                z[t][v] = (RowT)qt;
             }
         } else {
-            if (v == 0 && src_here) r -= a.h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
+            if (!FR && v == 0 && src_here) r -= src_term(b);
 #pragma unroll
             for (int bb = 0; bb < n; bb++)
-                if (bb == b) z[bb][v] = r;
+                if (bb == b) z[bb][v] = (RowT)r;
         }
     };
     // end of an iteration > 0: rows hold h R_b; replace them by the new iterate
-    auto update = [&]() {
+    auto update = [&](bool last) {
 #pragma unroll
         for (int v = 0; v < V; v++) {
             double r[n];
 #pragma unroll
-            for (int b = 0; b < n; b++) r[b] = z[b][v];
+            for (int b = 0; b < n; b++) {
+                r[b] = (double)z[b][v];
+                if (FR && v == 0 && src_here) r[b] -= src_term(b);
+            }
 #pragma unroll
             for (int t = 0; t < n; t++) {
                 double acc = 0.0;
 #pragma unroll
                 for (int b = 0; b < n; b++) acc = fma(B->Atau[t][b], r[b], acc);
-                z[t][v] = fma(-a.sigma, acc, Qn[v]);
+                const double qt = fma(-a.sigma, acc, Qn[v]);
+                if (FR && last) qbar[v] = fma(B->w[t], qt, qbar[v]);
+                z[t][v] = (RowT)qt;
             }
         }
     };
@@ -448,7 +464,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                     }
                 }
             }
-            if (it > 0 && active) update();
+            if (it > 0 && active) update(it == iters - 1);
         }
     } else {
         using T = typename Store<PP>::T;
@@ -469,7 +485,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 // the flux sees the FP32 rounding of the FP64 iterate
                 float qb[V];
 #pragma unroll
-                for (int v = 0; v < V; v++) qb[v] = (float)z[b][v];
+                for (int v = 0; v < V; v++) qb[v] = (float)z[b][v];  // exact when FR
                 if (slot) {
 #pragma unroll
                     for (int j = 0; j < DIM; j++) {
@@ -500,20 +516,21 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                     }
                 }
             }
-            if (it > 0 && active) update();
+            if (it > 0 && active) update(it == iters - 1);
         }
     }
     __syncthreads();
 
     // ---------------- time averages (FP64) ----------------
     // qbar here; the flux averages fbar_j are formed per direction below
-    double qbar[V], nbar[V];
+    double nbar[V];
 #pragma unroll
     for (int v = 0; v < V; v++) {
-        qbar[v] = 0.0;
         nbar[v] = 0.0;
+        if constexpr (!FR) {
 #pragma unroll
-        for (int t = 0; t < n; t++) qbar[v] = fma(B->w[t], z[t][v], qbar[v]);
+            for (int t = 0; t < n; t++) qbar[v] = fma(B->w[t], z[t][v], qbar[v]);
+        }
     }
     if constexpr (Pde::kNCP) {
         // average of the non-conservative product: sum_a w_a g h_a D_j eta_a
@@ -577,7 +594,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         // fbar_j = sum_a w_a F_j(q_a); for a linear flux this is F_j(qbar)
         double fbj[V];
         if constexpr (Pde::kLinear) {
-            Pde::flux(coef, qbar, j, fbj);
+            flux_dir<Pde, DIM>(coef, qbar, j, fbj);
         } else {
 #pragma unroll
             for (int v = 0; v < V; v++) fbj[v] = 0.0;
