@@ -105,6 +105,7 @@ __device__ __forceinline__ void lines_fp64(double *X, int nblk, MT M, DirOf dir_
 // Lanes whose output column is a padding position store to unused slots.
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef short i16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 
@@ -200,40 +201,149 @@ struct MfmaLines {
 };
 
 // ---------------------------------------------------------------------------
-// Picard line buffers.  Lines are numbered ((cb*DIM + j)*NV + v)*F + f: block
-// cell cb, direction j, variable v (NV = V, plus eta for the non-conservative
-// term), face node f.
-//  FP64:  position-major X[k][line] with an odd pitch NLP (conflict-free
-//         column access by consecutive lines), differentiated in place.
-//  other: line-major F[line][NB] (NB = 4 or 8 positions, zero padded) in the
-//         contraction format, so that a lane's 4 MFMA operand values are one
-//         8-byte load; FP32 results in the same layout.
+// Matrix-core derivative of variable pairs, inputs in format P (FP32, BF16 or
+// FP16), FP32 accumulation.  Data: for every line pair LP (one line geometry,
+// two variables), NPOS position slots (8, or 4 when n <= 4) x 2 variables,
+// position pairs swizzled by the face node f of the line: element
+// LP*2*NPOS + 4*((k/2) ^ sw(f)) + 2*(k%2) + var.  One 16x16 tile takes
+// LPC = 8/NPOS line pairs per column of the B operand (K = (line pair,
+// position, variable)); the constant A operand holds D on the interleaved
+// block diagonal (row (line pair, i, var), column (line pair, k, var)), so a
+// C column is the derivative of both variables of its line pairs.  FP32
+// results go to Y[LP*2*NPOS + 2*(i ^ osw(f)) + var].  Lane layouts (64 lanes,
+// 16x16xK): A[row = lane%16][k], B[k][col = lane%16],
+// C[row = 4*(lane/16) + e][col], with lane group g = lane/16 holding
+// k = 4g..4g+3 (16-bit formats), or one k per instruction ordered so that its
+// four values are one 16-byte load (FP32).  The swizzles spread the owner
+// writes and gathers over the LDS banks.
+// ---------------------------------------------------------------------------
+template <int n>
+struct PairGeom {
+    static constexpr int NPOS = n <= 4 ? 4 : 8;
+    static constexpr int LPC = 8 / NPOS;   // line pairs per tile column
+    static constexpr int PPL = NPOS / 2;   // position pairs per line
+    static constexpr int LSTRIDE = 2 * NPOS;
+    __device__ static constexpr int sw(int f) { return (f >> 2) & (PPL - 1); }
+    __device__ static constexpr int osw(int f) { return (f >> 2) & (NPOS - 1); }
+    __device__ static int in_off(int lp, int f, int k) { return lp * LSTRIDE + 4 * ((k >> 1) ^ sw(f)) + 2 * (k & 1); }
+    __device__ static int out_off(int lp, int f, int k) { return lp * LSTRIDE + 2 * (k ^ osw(f)); }
+};
+
+template <int P, int n>
+struct MfmaPairs {
+    using T = typename Store<P>::T;
+    using VT = typename std::conditional<P == PBF16, i16x4, f16x4>::type;
+    VT a;          // 16-bit formats: A operand
+    float am[4];   // FP32: A operand of each of the four 16x16x4 steps
+
+    using G = PairGeom<n>;
+    template <class MT>
+    __device__ void init(MT M, int lane) {
+        const int r = lane & 15, g = lane >> 4;
+        const int hr = r / G::LSTRIDE, i = (r % G::LSTRIDE) >> 1, vb = r & 1;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int k = 4 * g + e, hk = k / G::LSTRIDE, kp = (k % G::LSTRIDE) >> 1;
+            const float val = (hr == hk && (k & 1) == vb && i < n && kp < n) ? M[i][kp] : 0.0f;
+            if constexpr (P == P32) am[e] = val;
+            else if constexpr (P == PBF16) a[e] = __builtin_bit_cast(short, round_to<PBF16>(val));
+            else a[e] = round_to<PF16>(val);
+        }
+    }
+
+    template <int NTILE, int NWAVE, int F>
+    __device__ void run(const T *X, float *Y, int wave, int lane) const {
+        constexpr int TPW = (NTILE + NWAVE - 1) / NWAVE;
+        constexpr int TB = TPW < 4 ? TPW : 4;
+        const int c = lane & 15, g = lane >> 4, gh = g / G::PPL, gp = g % G::PPL;
+#pragma unroll
+        for (int k0 = 0; k0 < TPW; k0 += TB) {
+            f32x4 cc[TB];
+            int lp[TB], fo[TB];
+            if constexpr (P == P32) {
+                f32x4 bv[TB];
+#pragma unroll
+                for (int k = 0; k < TB; k++) {
+                    const int tile = wave + (k0 + k) * NWAVE;
+                    lp[k] = (tile * 16 + c) * G::LPC + gh;
+                    fo[k] = G::osw(lp[k] % F);
+                    if (k0 + k < TPW && tile < NTILE)
+                        bv[k] = *reinterpret_cast<const f32x4 *>(X + lp[k] * G::LSTRIDE + 4 * (gp ^ G::sw(lp[k] % F)));
+                }
+#pragma unroll
+                for (int k = 0; k < TB; k++) {
+                    const int tile = wave + (k0 + k) * NWAVE;
+                    if (k0 + k < TPW && tile < NTILE) {
+                        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int m = 0; m < 4; m++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(am[m], bv[k][m], acc, 0, 0, 0);
+                        cc[k] = acc;
+                    }
+                }
+            } else {
+                VT bv[TB];
+#pragma unroll
+                for (int k = 0; k < TB; k++) {
+                    const int tile = wave + (k0 + k) * NWAVE;
+                    lp[k] = (tile * 16 + c) * G::LPC + gh;
+                    fo[k] = G::osw(lp[k] % F);
+                    if (k0 + k < TPW && tile < NTILE)
+                        bv[k] = *reinterpret_cast<const VT *>(X + lp[k] * G::LSTRIDE + 4 * (gp ^ G::sw(lp[k] % F)));
+                }
+#pragma unroll
+                for (int k = 0; k < TB; k++) {
+                    const int tile = wave + (k0 + k) * NWAVE;
+                    if (k0 + k < TPW && tile < NTILE) {
+                        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+                        if constexpr (P == PBF16) cc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv[k], z, 0, 0, 0);
+                        else cc[k] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bv[k], z, 0, 0, 0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < TB; k++) {
+                const int tile = wave + (k0 + k) * NWAVE;
+                if (k0 + k < TPW && tile < NTILE) {
+                    float *y = Y + lp[k] * G::LSTRIDE;
+                    *reinterpret_cast<f32x2 *>(y + 2 * ((2 * gp) ^ fo[k])) = f32x2{cc[k][0], cc[k][1]};
+                    *reinterpret_cast<f32x2 *>(y + 2 * ((2 * gp + 1) ^ fo[k])) = f32x2{cc[k][2], cc[k][3]};
+                }
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Picard line buffers.
+//  FP64: lines numbered ((cb*DIM + j)*NV + v)*F + f (block cell cb, direction
+//        j, variable v (NV = V, plus eta for the non-conservative term), face
+//        node f), position-major X[k][line] with an odd pitch NLP
+//        (conflict-free column access by consecutive lines), differentiated in
+//        place.
+//  other: line pairs LP = ((cb*DIM + j)*NP + p)*F + f for the variable pairs
+//        (2p, 2p+1) (an odd NV is padded with a zero variable), in the
+//        MfmaPairs layout: the contraction format in, FP32 out.
 // ---------------------------------------------------------------------------
 template <class Pde, int DIM, int N, int PP>
 struct PicardLayout {
     using Sh = Shape<DIM, N>;
     static constexpr int n = Sh::n, F = Sh::F, CPB = Sh::CPB;
     static constexpr int NV = Pde::kNCP ? Pde::V + 1 : Pde::V;
+    // FP64
     static constexpr int NL = CPB * DIM * NV * F;
     static constexpr int NLP = NL | 1;
-    static constexpr int NB = n <= 4 ? 4 : 8;
-    static constexpr int LPR = 16 / NB;
-    static constexpr int LPT = 16 * LPR;
-    static constexpr int NTILE = (NL + LPT - 1) / LPT;
-    static constexpr int NLT = NTILE * LPT;
-    // element offset of position k on line `line`, and the offset between variables
-    __device__ static constexpr int elem(int line, int k) { return PP == P64 ? k * NLP + line : line * NB + k; }
-    static constexpr int VSTRIDE = PP == P64 ? F : F * NB;
-    // FP32 output layout of the matrix-core path: line-major with a padded line
-    // stride OSTRIDE = NB + NB/4, so that the four lane groups of a tile (whose
-    // rows are 4*LPR lines apart) write to different LDS banks.
-    static constexpr int OSTRIDE = NB + NB / 4;
-    static constexpr int OVSTRIDE = F * OSTRIDE;
-    static constexpr int OTILE = LPT * OSTRIDE;
-    __device__ static constexpr int oelem(int line, int k) { return line * OSTRIDE + k; }
-    static constexpr size_t obytes = (size_t)NTILE * OTILE * 4;
-    static constexpr size_t bytes =
-        PP == P64 ? (size_t)n * NLP * 8 : (size_t)NLT * NB * sizeof(typename Store<PP>::T) + obytes;
+    __device__ static constexpr int elem(int line, int k) { return k * NLP + line; }
+    static constexpr int VSTRIDE = F;
+    // lower formats
+    using G = PairGeom<n>;
+    static constexpr int NP = (NV + 1) / 2;
+    static constexpr int NLPR = CPB * DIM * NP * F;
+    static constexpr int NTILE = (NLPR + 16 * G::LPC - 1) / (16 * G::LPC);
+    static constexpr int PSTRIDE = G::LSTRIDE * F;  // elements (and floats) between variable pairs
+    static constexpr size_t esz = PP == P64 ? 8 : sizeof(typename Store<PP>::T);
+    static constexpr size_t in_bytes = (size_t)NTILE * 16 * 16 * esz;
+    static constexpr size_t out_bytes = (size_t)NTILE * 16 * 16 * 4;
+    static constexpr size_t bytes = PP == P64 ? (size_t)n * NLP * 8 : in_bytes + out_bytes;
 };
 
 // ---------------------------------------------------------------------------
@@ -366,12 +476,12 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
 #pragma unroll
     for (int v = 0; v < V; v++) qbar[v] = 0.0;
     // per-thread offset of its node in each direction's lines (variable 0)
-    int po[DIM], pr[DIM];
+    int po[DIM];
 #pragma unroll
     for (int j = 0; j < DIM; j++) {
-        const int line0 = ((cb * DIM + j) * NV) * F + face_of<n, DIM>(s, j);
-        po[j] = PL::elem(line0, coord<n>(s, j));
-        pr[j] = PL::oelem(line0, coord<n>(s, j));
+        const int f = face_of<n, DIM>(s, j), k = coord<n>(s, j);
+        if constexpr (PP == P64) po[j] = PL::elem(((cb * DIM + j) * NV) * F + f, k);
+        else po[j] = ((cb * DIM + j) * PL::NP) * F + f;
     }
     auto src_term = [&](int b) {
         return a.h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
@@ -468,15 +578,23 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         }
     } else {
         using T = typename Store<PP>::T;
-        constexpr int NB = PL::NB;
-        T *Fb = reinterpret_cast<T *>(smem);                                    // [NLT][NB] line-major
-        float *Rb = reinterpret_cast<float *>(smem + (size_t)PL::NLT * NB * sizeof(T));  // [NLT][OSTRIDE]
-        // zero padding (positions >= n and lines >= NL are never written)
-        for (int i = tid; i < PL::NLT * NB; i += TPB) Fb[i] = round_to<PP>(0.0f);
+        T *Fb = reinterpret_cast<T *>(smem);
+        float *Rb = reinterpret_cast<float *>(smem + PL::in_bytes);
+        // zero the operand buffer once: padding positions, the padding variable
+        // of an odd pair and the padding line pairs stay zero
+        for (int i = tid; i < (int)(PL::in_bytes / 4); i += TPB) reinterpret_cast<uint32_t *>(smem)[i] = 0u;
         const int lane = tid & 63, wave = tid >> 6;
         constexpr int NWAVE = TPB / 64;
-        MfmaLines<PP, n> ml;
-        ml.init(B->Dp[PP], lane);
+        MfmaPairs<PP, n> mp;
+        mp.init(B->Dp[PP], lane);
+        int io[DIM], oo[DIM];
+#pragma unroll
+        for (int j = 0; j < DIM; j++) {
+            const int f = face_of<n, DIM>(s, j), k = coord<n>(s, j);
+            io[j] = PL::G::in_off(po[j], f, k);
+            oo[j] = PL::G::out_off(po[j], f, k);
+        }
+        __syncthreads();
 #pragma unroll 1
         for (int it = 0; it < iters; it++) {
 #pragma unroll
@@ -489,28 +607,49 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 if (slot) {
 #pragma unroll
                     for (int j = 0; j < DIM; j++) {
-                        float Fv[V];
+                        float Fv[2 * PL::NP];
                         Pde::flux(coef, qb, j, Fv);
+                        if constexpr (Pde::kNCP) Fv[V] = Pde::ncp_input(qb);
 #pragma unroll
-                        for (int v = 0; v < V; v++) Fb[po[j] + v * PL::VSTRIDE] = round_to<PP>(Fv[v]);
-                        if constexpr (Pde::kNCP) Fb[po[j] + V * PL::VSTRIDE] = round_to<PP>(Pde::ncp_input(qb));
+                        for (int v = NV; v < 2 * PL::NP; v++) Fv[v] = 0.0f;
+#pragma unroll
+                        for (int p = 0; p < PL::NP; p++) {
+                            T *dst = Fb + io[j] + p * PL::PSTRIDE;
+                            if constexpr (PP == P32) {
+                                *reinterpret_cast<f32x2 *>(dst) = f32x2{Fv[2 * p], Fv[2 * p + 1]};
+                            } else {
+                                const uint32_t lo = __builtin_bit_cast(uint16_t, round_to<PP>(Fv[2 * p]));
+                                const uint32_t hi = __builtin_bit_cast(uint16_t, round_to<PP>(Fv[2 * p + 1]));
+                                *reinterpret_cast<uint32_t *>(dst) = lo | (hi << 16);
+                            }
+                        }
                     }
                 }
                 __syncthreads();
-                ml.template run<PL::NTILE, NWAVE>(Fb, Rb, wave);
+                mp.template run<PL::NTILE, NWAVE, F>(Fb, Rb, wave, lane);
                 __syncthreads();
                 if (active) {
+                    // the divergence sum over directions is part of the FP32
+                    // contraction
+                    float rf[2 * PL::NP], eta[DIM];
+#pragma unroll
+                    for (int v = 0; v < 2 * PL::NP; v++) rf[v] = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < DIM; j++) {
+#pragma unroll
+                        for (int p = 0; p < PL::NP; p++) {
+                            const f32x2 r2 = *reinterpret_cast<const f32x2 *>(Rb + oo[j] + p * PL::PSTRIDE);
+                            if (2 * p < V) rf[2 * p] += r2[0];
+                            if (2 * p + 1 < V) rf[2 * p + 1] += r2[1];
+                            if (Pde::kNCP && 2 * p == V) eta[j] = r2[0];
+                            if (Pde::kNCP && 2 * p + 1 == V) eta[j] = r2[1];
+                        }
+                    }
 #pragma unroll
                     for (int v = V - 1; v >= 0; v--) {
-                        // the divergence sum over directions is part of the FP32
-                        // contraction
-                        float rf = 0.0f;
-#pragma unroll
-                        for (int j = 0; j < DIM; j++) rf += Rb[pr[j] + v * PL::OVSTRIDE];
-                        double rr = (double)rf;
+                        double rr = (double)rf[v];
                         if constexpr (Pde::kNCP) {
-                            if (v >= 1 && v <= DIM)
-                                rr += (double)((float)coef.g * qb[0] * Rb[pr[v - 1] + V * PL::OVSTRIDE]);
+                            if (v >= 1 && v <= DIM) rr += (double)((float)coef.g * qb[0] * eta[v - 1]);
                         }
                         fold(it, b, v, rr);
                     }
