@@ -91,114 +91,10 @@ __device__ __forceinline__ void lines_fp64(double *X, int nblk, MT M, DirOf dir_
     }
 }
 
-// ---------------------------------------------------------------------------
-// Matrix-core line contraction Y = M along every line of a block, inputs in
-// format P (FP32, BF16 or FP16), FP32 accumulation.  Input: line-major,
-// zero-padded X[line][NB] (NB = 8, or 4 when n <= 4).  Output: line-major Y
-// with padded stride OSTRIDE.  A 16x16 tile holds LPR = 16/NB lines per row;
-// the B operand is the constant block-diagonal diag(M^T, ..., M^T), so one
-// tile contracts 16*LPR lines.  Lane layouts (64 lanes, 16x16xK):
-// A[row = lane%16][k = 4*(lane/16) + e], B[k][col = lane%16],
-// C[row = 4*(lane/16) + e][col = lane%16].  Every lane-dependent offset is
-// fixed at init(); run() issues the wave's tiles in batches (loads, then the
-// independent MFMAs, then the stores) so LDS and matrix-core latencies overlap.
-// Lanes whose output column is a padding position store to unused slots.
-// ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef short i16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
-
-template <int P, int n>
-struct MfmaLines {
-    using T = typename Store<P>::T;
-    static constexpr int NB = n <= 4 ? 4 : 8;
-    static constexpr int LPR = 16 / NB;
-    static constexpr int LPT = 16 * LPR;
-    static constexpr int OSTRIDE = NB + NB / 4;
-    static constexpr int OTILE = LPT * OSTRIDE;
-    using VT = typename std::conditional<P == PBF16, i16x4, f16x4>::type;
-    VT bvec;
-    float bm[4];
-    int aoff, aoffm[4], coff;
-
-    template <class MT>
-    __device__ void init(MT M, int lane) {
-        const int r = lane & 15, g = lane >> 4;
-        auto bval = [&](int k) -> float {
-            const int kb = k / NB, kk = k % NB, cbk = r / NB, cc = r % NB;
-            return (kb == cbk && kk < n && cc < n) ? M[cc][kk] : 0.0f;
-        };
-#pragma unroll
-        for (int m = 0; m < 4; m++) {
-            const int k = 4 * m + g;
-            bm[m] = bval(k);
-            aoffm[m] = (LPR * r + k / NB) * NB + k % NB;
-        }
-        aoff = (LPR * r + (4 * g) / NB) * NB + (4 * g) % NB;
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-            if constexpr (P == PBF16) bvec[e] = __builtin_bit_cast(short, round_to<PBF16>(bval(4 * g + e)));
-            else if constexpr (P == PF16) bvec[e] = round_to<PF16>(bval(4 * g + e));
-        }
-        coff = (LPR * 4 * g + r / NB) * OSTRIDE + r % NB;
-    }
-
-    template <int NTILE, int NWAVE>
-    __device__ void run(const T *X, float *Y, int wave) const {
-        constexpr int TPW = (NTILE + NWAVE - 1) / NWAVE;
-        constexpr int TB = TPW < 4 ? TPW : 4;
-#pragma unroll
-        for (int k0 = 0; k0 < TPW; k0 += TB) {
-            f32x4 cc[TB];
-            if constexpr (P == P32) {
-                float av[TB][4];
-#pragma unroll
-                for (int k = 0; k < TB; k++) {
-                    const int tile = wave + (k0 + k) * NWAVE;
-                    if (k0 + k < TPW && tile < NTILE) {
-#pragma unroll
-                        for (int m = 0; m < 4; m++) av[k][m] = X[tile * LPT * NB + aoffm[m]];
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < TB; k++) {
-                    const int tile = wave + (k0 + k) * NWAVE;
-                    if (k0 + k < TPW && tile < NTILE) {
-                        f32x4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                        for (int m = 0; m < 4; m++) c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[k][m], bm[m], c, 0, 0, 0);
-                        cc[k] = c;
-                    }
-                }
-            } else {
-                VT av[TB];
-#pragma unroll
-                for (int k = 0; k < TB; k++) {
-                    const int tile = wave + (k0 + k) * NWAVE;
-                    if (k0 + k < TPW && tile < NTILE) av[k] = *reinterpret_cast<const VT *>(X + tile * LPT * NB + aoff);
-                }
-#pragma unroll
-                for (int k = 0; k < TB; k++) {
-                    const int tile = wave + (k0 + k) * NWAVE;
-                    if (k0 + k < TPW && tile < NTILE) {
-                        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-                        if constexpr (P == PBF16) cc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[k], bvec, z, 0, 0, 0);
-                        else cc[k] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[k], bvec, z, 0, 0, 0);
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < TB; k++) {
-                const int tile = wave + (k0 + k) * NWAVE;
-                if (k0 + k < TPW && tile < NTILE) {
-#pragma unroll
-                    for (int e = 0; e < 4; e++) Y[tile * OTILE + coff + LPR * OSTRIDE * e] = cc[k][e];
-                }
-            }
-        }
-    }
-};
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------------------
 // Matrix-core derivative of variable pairs, inputs in format P (FP32, BF16 or
@@ -350,8 +246,7 @@ struct PicardLayout {
 // Epilogue line buffers (face projection and volume integral), one direction
 // at a time.  Input: position-major FP64 Ein[k][line] for the lines
 // (cell, q|f, var, face node), odd pitch.  Volume output: FP64 Evol[i][line]
-// for the lines (cell, var, face node), or, for a lower volume format, the
-// matrix-core operands (line-major input sized for FP32, FP32 output).
+// for the lines (cell, var, face node).
 // ---------------------------------------------------------------------------
 template <class Pde, int DIM, int N>
 struct EpiLayout {
@@ -361,13 +256,7 @@ struct EpiLayout {
     static constexpr int NLE = 2 * NLV;
     static constexpr int NLPE = NLE | 1, NLPV = NLV | 1;
     static constexpr size_t in_bytes = (size_t)n * NLPE * 8;
-    using ML = MfmaLines<P32, n>;  // tile geometry is the same for every format
-    static constexpr int NTILE = (NLV + ML::LPT - 1) / ML::LPT;
-    static constexpr size_t mfma_in = (size_t)NTILE * ML::LPT * ML::NB * 4;
-    static constexpr size_t mfma_out = (size_t)NTILE * ML::OTILE * 4;
-    static constexpr size_t vol64 = (size_t)n * NLPV * 8;
-    static constexpr size_t vol_bytes = vol64 > mfma_in + mfma_out ? vol64 : mfma_in + mfma_out;
-    static constexpr size_t bytes = in_bytes + vol_bytes;
+    static constexpr size_t bytes = in_bytes + (size_t)n * NLPV * 8;
 };
 
 // ---------------------------------------------------------------------------
@@ -698,35 +587,19 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     // ---------------- face projection and volume integral ----------------
     // Per direction j: the owners write qbar and fbar_j at their position on
     // the lines along j; one thread per (cell, var, face node) projects both
-    // lines onto the two faces (Alg. 1 "expansion") and, for an FP64 volume,
-    // applies Kxi along the fbar_j line; a lower volume format runs the same
-    // contraction on the matrix cores.  The owners then gather their node's
-    // volume term.  Two barriers per direction: the line pass reads Ein and
-    // writes the volume buffer, which the owners only read after the second
-    // barrier and only overwrite (Ein) after it.
+    // lines onto the two faces (Alg. 1 "expansion") and applies Kxi along the
+    // fbar_j line (FP64, or inputs rounded to the volume format with FP32
+    // accumulation: one contraction per direction, so the vector ALU serves).
+    // The owners then gather their node's volume term.  Two barriers per
+    // direction: the line pass reads Ein and writes Evol, which the owners
+    // only read after the second barrier and only overwrite (Ein) after it.
     using EL = EpiLayout<Pde, DIM, N>;
     double *Ein = reinterpret_cast<double *>(smem);                  // [n][NLPE]
     double *Evol = reinterpret_cast<double *>(smem + EL::in_bytes);  // [n][NLPV]
-    char *Mx = smem + EL::in_bytes;                                   // matrix-core input
-    float *My = reinterpret_cast<float *>(smem + EL::in_bytes + EL::mfma_in);
     const int vp = a.vol_prec;
-    if (vp != P64) {
-        // zero padding of the line-major operands (positions >= n, lines >= NLV);
-        // the owners never write these slots, so no barrier is needed here
-        constexpr int NB = EL::ML::NB;
-        const int esz = vp == P32 ? 4 : 2;
-        for (int idx = tid; idx < EL::NTILE * EL::ML::LPT * NB; idx += TPB) {
-            if (idx % NB >= n || idx / NB >= EL::NLV) {
-                if (esz == 4) reinterpret_cast<float *>(Mx)[idx] = 0.0f;
-                else reinterpret_cast<unsigned short *>(Mx)[idx] = 0;
-            }
-        }
-    }
     double vol[V];
 #pragma unroll
     for (int v = 0; v < V; v++) vol[v] = 0.0;
-    const int lane = tid & 63, wave = tid >> 6;
-    constexpr int NWAVE = TPB / 64;
 
 #pragma unroll 1
     for (int j = 0; j < DIM; j++) {
@@ -754,32 +627,8 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 Ein[ij * EL::NLPE + ((cb * 2 + 0) * V + v) * F + fj] = active ? qbar[v] : 0.0;
                 Ein[ij * EL::NLPE + ((cb * 2 + 1) * V + v) * F + fj] = active ? fbj[v] : 0.0;
             }
-            if (vp != P64) {
-                const int l0 = (cb * V) * F + fj;
-#pragma unroll
-                for (int v = 0; v < V; v++) {
-                    const float x = active ? (float)fbj[v] : 0.0f;
-                    const int e = (l0 + v * F) * EL::ML::NB + ij;
-                    if (vp == P32) reinterpret_cast<float *>(Mx)[e] = x;
-                    else if (vp == PBF16) reinterpret_cast<__hip_bfloat16 *>(Mx)[e] = round_to<PBF16>(x);
-                    else reinterpret_cast<_Float16 *>(Mx)[e] = round_to<PF16>(x);
-                }
-            }
         }
         __syncthreads();
-        if (vp == P32) {
-            MfmaLines<P32, n> ml;
-            ml.init(B->Kxip[P32], lane);
-            ml.template run<EL::NTILE, NWAVE>(reinterpret_cast<const float *>(Mx), My, wave);
-        } else if (vp == PBF16) {
-            MfmaLines<PBF16, n> ml;
-            ml.init(B->Kxip[PBF16], lane);
-            ml.template run<EL::NTILE, NWAVE>(reinterpret_cast<const __hip_bfloat16 *>(Mx), My, wave);
-        } else if (vp == PF16) {
-            MfmaLines<PF16, n> ml;
-            ml.init(B->Kxip[PF16], lane);
-            ml.template run<EL::NTILE, NWAVE>(reinterpret_cast<const _Float16 *>(Mx), My, wave);
-        }
         auto line_pass = [&](auto fpc) {
             constexpr int FP = decltype(fpc)::value;
             for (int L = tid; L < EL::NLV; L += TPB) {
@@ -807,6 +656,20 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                         for (int k = 0; k < n; k++) y = fma(B->Kxi[i][k], xf[k], y);
                         Evol[i * EL::NLPV + L] = y;
                     }
+                } else {
+                    float xr[n];
+#pragma unroll
+                    for (int k = 0; k < n; k++) {
+                        const float x = (float)xf[k];
+                        xr[k] = vp == P32 ? x : (vp == PBF16 ? widen(round_to<PBF16>(x)) : widen(round_to<PF16>(x)));
+                    }
+#pragma unroll
+                    for (int i = 0; i < n; i++) {
+                        float y = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < n; k++) y += B->Kxip[vp][i][k] * xr[k];
+                        Evol[i * EL::NLPV + L] = (double)y;
+                    }
                 }
             }
         };
@@ -819,13 +682,8 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         __syncthreads();
         if (active) {
             const int l0 = (cb * V) * F + fj;
-            if (vp == P64) {
 #pragma unroll
-                for (int v = 0; v < V; v++) vol[v] += Evol[ij * EL::NLPV + l0 + v * F];
-            } else {
-#pragma unroll
-                for (int v = 0; v < V; v++) vol[v] += (double)My[(l0 + v * F) * EL::ML::OSTRIDE + ij];
-            }
+            for (int v = 0; v < V; v++) vol[v] += Evol[ij * EL::NLPV + l0 + v * F];
         }
     }
 
