@@ -15,6 +15,7 @@ per step); every variant's throughput, speed-up over FP64 and L2 error
 are in `runs`.  Inputs are resident in HBM before the timed region.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -60,6 +61,39 @@ def predictor_bytes(d, N, V, face_bytes):
     S = n ** d
     F = S // n
     return 2 * S * V * 8 + 2 * d * 2 * V * F * face_bytes
+
+
+# Sources that determine the machine code of k_predictor for this workload.
+KERNEL_SOURCES = ("paper_2504_06889_amd/csrc/common.h", "paper_2504_06889_amd/csrc/kernels.h",
+                  "paper_2504_06889_amd/csrc/inst_elastic3.hip", "paper_2504_06889_amd/build.py")
+TRAFFIC_FILE = "profiles/k_predictor_elastic3d_n5_64_hbm_traffic.md"
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Per-launch HBM bytes of k_predictor from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (scaled by a plain copy's counter readings), or {} when the
+    kernel sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return {}
+    out, ok = {}, False
+    with open(path) as fh:
+        for line in fh:
+            t = line.strip()
+            if t.startswith("kernel-source-sha256:"):
+                ok = t.split(":", 1)[1].strip() == kernel_source_hash()
+            elif t.startswith("traffic-bytes-per-launch"):
+                key, val = t[len("traffic-bytes-per-launch"):].split(":")
+                out[key.strip()] = int(val)
+    return out if ok else {}
 
 
 def l2(W, h, d, A, B=None):
@@ -236,6 +270,7 @@ def main():
             runs[p]["speedup_vs_fp64"] = runs["fp64"]["ms_per_step"] / runs[p]["ms_per_step"]
 
     # roofline of the dominant kernel (the predictor) for each variant
+    traffic = measured_traffic() if args.workload == "elastic3d_n5_64" else {}
     I = g.iters
     mf, v64, fl = predictor_flops(sc.pde, sc.dim, sc.order, g.V, I)
     for p in runs:
@@ -252,7 +287,7 @@ def main():
         hbm = predictor_bytes(sc.dim, sc.order, g.V, 8) * g.ncell
         runs[p]["roofline"] = {
             "bound": bound, "achieved": total / t / 1e12, "peak": total / ideal / 1e12, "unit": "TFLOP/s",
-            "frac": ideal / t, "traffic": None,
+            "frac": ideal / t, "traffic": traffic.get(p),
             "flops_per_launch": total, "mfma_flops_per_launch": (mf * g.ncell if p != "fp64" else 0),
             "hbm_bytes_per_launch": hbm, "hbm_GBps": hbm / t / 1e9}
 
