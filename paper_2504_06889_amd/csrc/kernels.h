@@ -106,23 +106,24 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 // position, variable)); the constant A operand holds D on the interleaved
 // block diagonal (row (line pair, i, var), column (line pair, k, var)), so a
 // C column is the derivative of both variables of its line pairs.  FP32
-// results go to Y[LP*2*NPOS + 2*(i ^ osw(f)) + var].  Lane layouts (64 lanes,
+// results go to Y[LP*(2*NPOS + 2) + 2*i + var] (the padded line-pair stride
+// puts the 16 lanes of a 64-bit store on distinct banks).  Lane layouts (64 lanes,
 // 16x16xK): A[row = lane%16][k], B[k][col = lane%16],
 // C[row = 4*(lane/16) + e][col], with lane group g = lane/16 holding
 // k = 4g..4g+3 (16-bit formats), or one k per instruction ordered so that its
-// four values are one 16-byte load (FP32).  The swizzles spread the owner
-// writes and gathers over the LDS banks.
+// four values are one 16-byte load (FP32).  The input swizzle spreads the
+// owner writes over the LDS banks.
 // ---------------------------------------------------------------------------
 template <int n>
 struct PairGeom {
     static constexpr int NPOS = n <= 4 ? 4 : 8;
     static constexpr int LPC = 8 / NPOS;   // line pairs per tile column
     static constexpr int PPL = NPOS / 2;   // position pairs per line
-    static constexpr int LSTRIDE = 2 * NPOS;
+    static constexpr int LSTRIDE = 2 * NPOS;      // input elements per line pair
+    static constexpr int OSTRIDE = 2 * NPOS + 2;  // output floats per line pair
     __device__ static constexpr int sw(int f) { return (f >> 2) & (PPL - 1); }
-    __device__ static constexpr int osw(int f) { return (f >> 2) & (NPOS - 1); }
     __device__ static int in_off(int lp, int f, int k) { return lp * LSTRIDE + 4 * ((k >> 1) ^ sw(f)) + 2 * (k & 1); }
-    __device__ static int out_off(int lp, int f, int k) { return lp * LSTRIDE + 2 * (k ^ osw(f)); }
+    __device__ static int out_off(int lp, int k) { return lp * OSTRIDE + 2 * k; }
 };
 
 template <int P, int n>
@@ -155,14 +156,13 @@ struct MfmaPairs {
 #pragma unroll
         for (int k0 = 0; k0 < TPW; k0 += TB) {
             f32x4 cc[TB];
-            int lp[TB], fo[TB];
+            int lp[TB];
             if constexpr (P == P32) {
                 f32x4 bv[TB];
 #pragma unroll
                 for (int k = 0; k < TB; k++) {
                     const int tile = wave + (k0 + k) * NWAVE;
                     lp[k] = (tile * 16 + c) * G::LPC + gh;
-                    fo[k] = G::osw(lp[k] % F);
                     if (k0 + k < TPW && tile < NTILE)
                         bv[k] = *reinterpret_cast<const f32x4 *>(X + lp[k] * G::LSTRIDE + 4 * (gp ^ G::sw(lp[k] % F)));
                 }
@@ -182,7 +182,6 @@ struct MfmaPairs {
                 for (int k = 0; k < TB; k++) {
                     const int tile = wave + (k0 + k) * NWAVE;
                     lp[k] = (tile * 16 + c) * G::LPC + gh;
-                    fo[k] = G::osw(lp[k] % F);
                     if (k0 + k < TPW && tile < NTILE)
                         bv[k] = *reinterpret_cast<const VT *>(X + lp[k] * G::LSTRIDE + 4 * (gp ^ G::sw(lp[k] % F)));
                 }
@@ -200,9 +199,9 @@ struct MfmaPairs {
             for (int k = 0; k < TB; k++) {
                 const int tile = wave + (k0 + k) * NWAVE;
                 if (k0 + k < TPW && tile < NTILE) {
-                    float *y = Y + lp[k] * G::LSTRIDE;
-                    *reinterpret_cast<f32x2 *>(y + 2 * ((2 * gp) ^ fo[k])) = f32x2{cc[k][0], cc[k][1]};
-                    *reinterpret_cast<f32x2 *>(y + 2 * ((2 * gp + 1) ^ fo[k])) = f32x2{cc[k][2], cc[k][3]};
+                    float *y = Y + lp[k] * G::OSTRIDE + 4 * gp;
+                    *reinterpret_cast<f32x2 *>(y) = f32x2{cc[k][0], cc[k][1]};
+                    *reinterpret_cast<f32x2 *>(y + 2) = f32x2{cc[k][2], cc[k][3]};
                 }
             }
         }
@@ -235,10 +234,11 @@ struct PicardLayout {
     static constexpr int NP = (NV + 1) / 2;
     static constexpr int NLPR = CPB * DIM * NP * F;
     static constexpr int NTILE = (NLPR + 16 * G::LPC - 1) / (16 * G::LPC);
-    static constexpr int PSTRIDE = G::LSTRIDE * F;  // elements (and floats) between variable pairs
+    static constexpr int PSTRIDE = G::LSTRIDE * F;   // input elements between variable pairs
+    static constexpr int POSTRIDE = G::OSTRIDE * F;  // output floats between variable pairs
     static constexpr size_t esz = PP == P64 ? 8 : sizeof(typename Store<PP>::T);
     static constexpr size_t in_bytes = (size_t)NTILE * 16 * 16 * esz;
-    static constexpr size_t out_bytes = (size_t)NTILE * 16 * 16 * 4;
+    static constexpr size_t out_bytes = (size_t)NTILE * 16 * G::LPC * G::OSTRIDE * 4;
     static constexpr size_t bytes = PP == P64 ? (size_t)n * NLP * 8 : in_bytes + out_bytes;
 };
 
@@ -481,7 +481,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         for (int j = 0; j < DIM; j++) {
             const int f = face_of<n, DIM>(s, j), k = coord<n>(s, j);
             io[j] = PL::G::in_off(po[j], f, k);
-            oo[j] = PL::G::out_off(po[j], f, k);
+            oo[j] = PL::G::out_off(po[j], k);
         }
         __syncthreads();
 #pragma unroll 1
@@ -527,7 +527,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                     for (int j = 0; j < DIM; j++) {
 #pragma unroll
                         for (int p = 0; p < PL::NP; p++) {
-                            const f32x2 r2 = *reinterpret_cast<const f32x2 *>(Rb + oo[j] + p * PL::PSTRIDE);
+                            const f32x2 r2 = *reinterpret_cast<const f32x2 *>(Rb + oo[j] + p * PL::POSTRIDE);
                             if (2 * p < V) rf[2 * p] += r2[0];
                             if (2 * p + 1 < V) rf[2 * p + 1] += r2[1];
                             if (Pde::kNCP && 2 * p == V) eta[j] = r2[0];
