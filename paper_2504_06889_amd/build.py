@@ -20,6 +20,8 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=%s" % ARCH,
     # no packed FP32 instructions (v_pk_*_f32) anywhere
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # compile-time choice of LDS pitches (kernels.h, Fp64Pitch)
+    "-fconstexpr-steps=200000000",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]
 

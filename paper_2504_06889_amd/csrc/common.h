@@ -114,6 +114,8 @@ struct Acoustic {  // eq. acoustic: p_t + K div v = 0, rho v_t + grad p = 0
     }
     template <class T>
     __device__ static T speed(const Coef &c, const T *, int) { return (T)c.c; }
+    // F_j[v] is identically zero unless v is p or v_j
+    __host__ __device__ static constexpr bool flux_nz(int j, int v) { return v == 0 || v == 1 + j; }
 };
 
 template <int DIM>
@@ -155,6 +157,12 @@ struct Elastic {  // eq. equations_of_motion, q_t + A_j q_{x_j} = 0
     }
     template <class T>
     __device__ static T speed(const Coef &c, const T *, int) { return (T)c.cp; }
+    // F_j of a shear stress sigma_ab (a != b) is identically zero unless j is a or b
+    __host__ __device__ static constexpr bool flux_nz(int j, int v) {
+        if (v < DIM || v >= NS) return true;
+        if (DIM == 2) return true;
+        return v == 3 ? (j == 0 || j == 1) : (v == 4 ? (j == 1 || j == 2) : (j == 0 || j == 2));
+    }
 };
 
 template <int DIM>
@@ -185,6 +193,7 @@ struct Euler {  // conserved (rho, rho v, E), ideal gas
         const T p = pressure(c, q);
         return fabs(q[1 + j] / q[0]) + sqrt((T)c.g * p / q[0]);
     }
+    __host__ __device__ static constexpr bool flux_nz(int, int) { return true; }
 };
 
 struct Swe {  // (h, hu, hv, b); pressure term as non-conservative g h grad(h+b)
@@ -208,6 +217,8 @@ struct Swe {  // (h, hu, hv, b); pressure term as non-conservative g h grad(h+b)
     // eta = h + b, whose reference derivative feeds the non-conservative term
     template <class T>
     __device__ static T ncp_input(const T *q) { return q[0] + q[3]; }
+    // the bathymetry has no flux
+    __host__ __device__ static constexpr bool flux_nz(int, int v) { return v < 3; }
 };
 
 // Flux in a direction j that is only known at run time (but uniform): one

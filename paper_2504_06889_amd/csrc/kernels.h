@@ -209,29 +209,144 @@ struct MfmaPairs {
 };
 
 // ---------------------------------------------------------------------------
+// Flux components that enter the Picard divergence: F_j[v] for the v whose
+// flux is not identically zero in direction j, plus eta (index V) for the
+// non-conservative term.  Lines of identically zero fluxes are skipped (their
+// derivative is exactly zero).  The count is the same in every direction.
+// ---------------------------------------------------------------------------
+// eta for a system with a non-conservative term, else unused
+template <class Pde, class T>
+__device__ __forceinline__ T ncp_value(const T *q) {
+    if constexpr (Pde::kNCP) return Pde::ncp_input(q);
+    else return (T)0;
+}
+
+template <class Pde, int DIM>
+struct FluxSupport {
+    static constexpr int V = Pde::V;
+    static constexpr int NV = Pde::kNCP ? V + 1 : V;
+    __host__ __device__ static constexpr bool nz(int j, int v) { return v == V ? Pde::kNCP : Pde::flux_nz(j, v); }
+    __host__ __device__ static constexpr int count(int j) {
+        int c = 0;
+        for (int v = 0; v < NV; v++) c += nz(j, v) ? 1 : 0;
+        return c;
+    }
+    static constexpr int NZ = count(0);
+    // component of the idx-th line of direction j (-1: padding)
+    __host__ __device__ static constexpr int comp(int j, int idx) {
+        int c = 0;
+        for (int v = 0; v < NV; v++)
+            if (nz(j, v)) {
+                if (c == idx) return v;
+                c++;
+            }
+        return -1;
+    }
+    // line index of component v in direction j (-1: identically zero)
+    __host__ __device__ static constexpr int index(int j, int v) {
+        if (!nz(j, v)) return -1;
+        int c = 0;
+        for (int u = 0; u < v; u++) c += nz(j, u) ? 1 : 0;
+        return c;
+    }
+    static constexpr bool same_count() {
+        for (int j = 1; j < DIM; j++)
+            if (count(j) != NZ) return false;
+        return true;
+    }
+    static_assert(same_count(), "flux support must have the same size in every direction");
+};
+
+// ---------------------------------------------------------------------------
+// Pitch of the FP64 position-major line buffer X[k][line], chosen at compile
+// time among NL..NL+31 to minimise LDS bank conflicts of the owner accesses
+// (lane t of the block touches X[k*P + line] with k, line from its node), under
+// the bank model measured on gfx950: 64-bit writes are served 16 lanes at a
+// time on 32 four-byte banks (conflict when two lanes' doubles agree mod 16),
+// 64-bit reads 32 lanes at a time on 64 banks (doubles agree mod 32).  The
+// line pass touches consecutive lines and is conflict-free for any pitch.
+// ---------------------------------------------------------------------------
+template <int n, int DIM, int NZ, int CPB, int TPB>
+struct Fp64Pitch {
+    static constexpr int S = ipow(n, DIM), F = ipow(n, DIM - 1), NL = CPB * DIM * NZ * F;
+    struct Lanes {
+        int k[TPB][DIM], base[TPB][DIM];  // k = -1: no node
+    };
+    static constexpr Lanes lanes() {
+        Lanes L{};
+        for (int t = 0; t < TPB; t++) {
+            const int cb = t / S, s = t % S;
+            for (int j = 0; j < DIM; j++) {
+                const int crd = j == 0 ? s % n : (j == 1 ? (s / n) % n : s / (n * n));
+                const int fce = DIM == 2 ? (j == 0 ? s / n : s % n)
+                                         : (j == 0 ? s / n : (j == 1 ? (s % n) + n * (s / (n * n)) : s % (n * n)));
+                L.k[t][j] = cb < CPB ? crd : -1;
+                L.base[t][j] = (cb * DIM + j) * NZ * F + fce;
+            }
+        }
+        return L;
+    }
+    static constexpr int cost(const Lanes &L, int P) {
+        int c = 0;
+        // every flux component shifts all lanes' lines by the same i*F, which
+        // permutes the banks: the count is the same for each of the NZ components
+        for (int w = 0; w < TPB / 64; w++)
+            for (int j = 0; j < DIM; j++)
+                for (int g = 0; g < 6; g++) {  // 4 write quarters (mod 16), 2 read halves (mod 32)
+                    const int first = g < 4 ? 16 * g : 32 * (g - 4), len = g < 4 ? 16 : 32, mask = len - 1;
+                    int cnt[32] = {};
+                    int mx = 0;
+                    for (int l = w * 64 + first; l < w * 64 + first + len; l++) {
+                        if (L.k[l][j] < 0) continue;
+                        const int b = (L.k[l][j] * P + L.base[l][j]) & mask;
+                        mx = ++cnt[b] > mx ? cnt[b] : mx;
+                    }
+                    c += mx > 1 ? mx - 1 : 0;
+                }
+        return c * NZ;
+    }
+    static constexpr int best() {
+        const Lanes L = lanes();
+        int bp = NL | 1, bc = cost(L, NL | 1);
+        for (int P = NL; P < NL + 32; P++) {
+            const int c = cost(L, P);
+            if (c < bc) {
+                bc = c;
+                bp = P;
+            }
+        }
+        return bp;
+    }
+    static constexpr int value = best();
+};
+struct NoPitch {
+    static constexpr int value = 1;
+};
+
+// ---------------------------------------------------------------------------
 // Picard line buffers.
-//  FP64: lines numbered ((cb*DIM + j)*NV + v)*F + f (block cell cb, direction
-//        j, variable v (NV = V, plus eta for the non-conservative term), face
-//        node f), position-major X[k][line] with an odd pitch NLP
-//        (conflict-free column access by consecutive lines), differentiated in
-//        place.
-//  other: line pairs LP = ((cb*DIM + j)*NP + p)*F + f for the variable pairs
-//        (2p, 2p+1) (an odd NV is padded with a zero variable), in the
+//  FP64: lines numbered ((cb*DIM + j)*NZ + i)*F + f (block cell cb, direction
+//        j, i-th flux component of FluxSupport, face node f), position-major
+//        X[k][line] with the pitch NLP of Fp64Pitch, differentiated in place.
+//  other: line pairs LP = ((cb*DIM + j)*NP + p)*F + f for the component pairs
+//        (2p, 2p+1) (an odd NZ is padded with a zero component), in the
 //        MfmaPairs layout: the contraction format in, FP32 out.
 // ---------------------------------------------------------------------------
 template <class Pde, int DIM, int N, int PP>
 struct PicardLayout {
     using Sh = Shape<DIM, N>;
     static constexpr int n = Sh::n, F = Sh::F, CPB = Sh::CPB;
-    static constexpr int NV = Pde::kNCP ? Pde::V + 1 : Pde::V;
+    using FS = FluxSupport<Pde, DIM>;
+    static constexpr int NZ = FS::NZ;
     // FP64
-    static constexpr int NL = CPB * DIM * NV * F;
-    static constexpr int NLP = NL | 1;
+    static constexpr int NL = CPB * DIM * NZ * F;
+    static constexpr int NLP =
+        std::conditional<PP == P64, Fp64Pitch<n, DIM, NZ, CPB, Sh::TPB>, NoPitch>::type::value;
     __device__ static constexpr int elem(int line, int k) { return k * NLP + line; }
     static constexpr int VSTRIDE = F;
     // lower formats
     using G = PairGeom<n>;
-    static constexpr int NP = (NV + 1) / 2;
+    static constexpr int NP = (NZ + 1) / 2;
     static constexpr int NLPR = CPB * DIM * NP * F;
     static constexpr int NTILE = (NLPR + 16 * G::LPC - 1) / (16 * G::LPC);
     static constexpr int PSTRIDE = G::LSTRIDE * F;   // input elements between variable pairs
@@ -369,7 +484,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
 #pragma unroll
     for (int j = 0; j < DIM; j++) {
         const int f = face_of<n, DIM>(s, j), k = coord<n>(s, j);
-        if constexpr (PP == P64) po[j] = PL::elem(((cb * DIM + j) * NV) * F + f, k);
+        if constexpr (PP == P64) po[j] = PL::elem(((cb * DIM + j) * PL::NZ) * F + f, k);
         else po[j] = ((cb * DIM + j) * PL::NP) * F + f;
     }
     auto src_term = [&](int b) {
@@ -431,8 +546,10 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                         double Fv[V];
                         Pde::flux(coef, z[b], j, Fv);
 #pragma unroll
-                        for (int v = 0; v < V; v++) X[po[j] + v * PL::VSTRIDE] = Fv[v];
-                        if constexpr (Pde::kNCP) X[po[j] + V * PL::VSTRIDE] = Pde::ncp_input(z[b]);
+                        for (int i = 0; i < PL::NZ; i++) {
+                            const int c = PL::FS::comp(j, i);
+                            X[po[j] + i * PL::VSTRIDE] = c == V ? ncp_value<Pde>(z[b]) : Fv[c < V ? c : 0];
+                        }
                     }
                 }
                 __syncthreads();
@@ -455,9 +572,13 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                     for (int v = V - 1; v >= 0; v--) {
                         double r = 0.0;
 #pragma unroll
-                        for (int j = 0; j < DIM; j++) r += X[po[j] + v * PL::VSTRIDE];
+                        for (int j = 0; j < DIM; j++) {
+                            const int i = PL::FS::index(j, v);
+                            if (i >= 0) r += X[po[j] + i * PL::VSTRIDE];
+                        }
                         if constexpr (Pde::kNCP) {
-                            if (v >= 1 && v <= DIM) r += coef.g * z[b][0] * X[po[v - 1] + V * PL::VSTRIDE];
+                            if (v >= 1 && v <= DIM)
+                                r += coef.g * z[b][0] * X[po[v - 1] + PL::FS::index(v - 1, V) * PL::VSTRIDE];
                         }
                         fold(it, b, v, r);
                     }
@@ -496,19 +617,20 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 if (slot) {
 #pragma unroll
                     for (int j = 0; j < DIM; j++) {
-                        float Fv[2 * PL::NP];
+                        float Fv[V];
                         Pde::flux(coef, qb, j, Fv);
-                        if constexpr (Pde::kNCP) Fv[V] = Pde::ncp_input(qb);
-#pragma unroll
-                        for (int v = NV; v < 2 * PL::NP; v++) Fv[v] = 0.0f;
+                        auto comp_val = [&](int c) -> float {
+                            return c < 0 ? 0.0f : (c == V ? ncp_value<Pde>(qb) : Fv[c < V ? c : 0]);
+                        };
 #pragma unroll
                         for (int p = 0; p < PL::NP; p++) {
                             T *dst = Fb + io[j] + p * PL::PSTRIDE;
+                            const float f0 = comp_val(PL::FS::comp(j, 2 * p)), f1 = comp_val(PL::FS::comp(j, 2 * p + 1));
                             if constexpr (PP == P32) {
-                                *reinterpret_cast<f32x2 *>(dst) = f32x2{Fv[2 * p], Fv[2 * p + 1]};
+                                *reinterpret_cast<f32x2 *>(dst) = f32x2{f0, f1};
                             } else {
-                                const uint32_t lo = __builtin_bit_cast(uint16_t, round_to<PP>(Fv[2 * p]));
-                                const uint32_t hi = __builtin_bit_cast(uint16_t, round_to<PP>(Fv[2 * p + 1]));
+                                const uint32_t lo = __builtin_bit_cast(uint16_t, round_to<PP>(f0));
+                                const uint32_t hi = __builtin_bit_cast(uint16_t, round_to<PP>(f1));
                                 *reinterpret_cast<uint32_t *>(dst) = lo | (hi << 16);
                             }
                         }
@@ -520,18 +642,20 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 if (active) {
                     // the divergence sum over directions is part of the FP32
                     // contraction
-                    float rf[2 * PL::NP], eta[DIM];
+                    float rf[V], eta[DIM];
 #pragma unroll
-                    for (int v = 0; v < 2 * PL::NP; v++) rf[v] = 0.0f;
+                    for (int v = 0; v < V; v++) rf[v] = 0.0f;
 #pragma unroll
                     for (int j = 0; j < DIM; j++) {
 #pragma unroll
                         for (int p = 0; p < PL::NP; p++) {
                             const f32x2 r2 = *reinterpret_cast<const f32x2 *>(Rb + oo[j] + p * PL::POSTRIDE);
-                            if (2 * p < V) rf[2 * p] += r2[0];
-                            if (2 * p + 1 < V) rf[2 * p + 1] += r2[1];
-                            if (Pde::kNCP && 2 * p == V) eta[j] = r2[0];
-                            if (Pde::kNCP && 2 * p + 1 == V) eta[j] = r2[1];
+#pragma unroll
+                            for (int h = 0; h < 2; h++) {
+                                const int c = PL::FS::comp(j, 2 * p + h);
+                                if (c >= 0 && c < V) rf[c < V ? c : 0] += r2[h];
+                                if (Pde::kNCP && c == V) eta[j] = r2[h];
+                            }
                         }
                     }
 #pragma unroll
