@@ -64,50 +64,56 @@ __global__ __launch_bounds__(256) void k_lamface(const double *lam, double *out,
     }
 }
 
-// Position-major FP64 line pass: Xout[i][L] = sum_k M(i,k) Xin[k][L] with
-// M(i,k) = T ? Mat[k][i] : Mat[i][k].
-template <int n, bool T>
-__device__ __forceinline__ void lines_pm(const double *Xin, double *Xout, int NL, int NLP,
-                                         const double (*Mat)[kMaxN], int tid, int nthreads) {
-    for (int Ln = tid; Ln < NL; Ln += nthreads) {
+// In-place position-major FP64 line pass over the lines line_of(L), L < nl:
+// X[i][line] <- sum_k M(i,k) X[k][line] with M(i,k) = T ? Mat[k][i] : Mat[i][k].
+template <int n, bool T, class MT, class LineOf>
+__device__ __forceinline__ void lines_inplace(double *X, int nl, int NLP, MT Mat, LineOf line_of, int tid,
+                                              int nthreads) {
+    for (int L = tid; L < nl; L += nthreads) {
+        const int Ln = line_of(L);
         double x[n];
 #pragma unroll
-        for (int k = 0; k < n; k++) x[k] = Xin[k * NLP + Ln];
+        for (int k = 0; k < n; k++) x[k] = X[k * NLP + Ln];
 #pragma unroll
         for (int i = 0; i < n; i++) {
             double y = 0.0;
 #pragma unroll
             for (int k = 0; k < n; k++) y = fma(T ? Mat[k][i] : Mat[i][k], x[k], y);
-            Xout[i * NLP + Ln] = y;
+            X[i * NLP + Ln] = y;
         }
     }
 }
 
+// Line slots per direction j and cell: 0: F_j[0] = K v_j, 1: F_j[1+j] = p/rho
+// (the only non-zero components of the acoustic flux), 2, 3: their
+// K-tangents.  The adjoint passes use slots 0 and 1.
 template <int DIM, int N>
 struct AdjLayout {
     using Sh = Shape<DIM, N>;
     static constexpr int n = Sh::n, F = Sh::F, CPB = Sh::CPB, S = Sh::S;
     static constexpr int V = 1 + DIM;
-    static constexpr int NL = CPB * DIM * 2 * V * F;  // forward + tangent lines
-    static constexpr int NLP = NL | 1;
-    static constexpr size_t picard = (size_t)2 * n * NLP * 8;
+    static constexpr int NZ = 4;
+    static constexpr int NL = CPB * DIM * NZ * F;
+    static constexpr int NLP = Fp64Pitch<n, DIM, NZ, CPB, Sh::TPB>::value;
+    static constexpr size_t picard = (size_t)n * NLP * 8;
     static constexpr size_t faces = (size_t)2 * CPB * DIM * 2 * V * F * 8;  // q- and f-face adjoints
     static constexpr size_t bytes = (picard > faces ? picard : faces) + (size_t)CPB * 8 * 4;
+    // line of the L-th slot-0/1 line (L < CPB*DIM*2*F)
+    __device__ static int half_line(int L) { return (L / (2 * F)) * (NZ * F) + L % (2 * F); }
 };
 
 template <int DIM, int N>
-__global__ __launch_bounds__((Shape<DIM, N>::TPB)) void k_adjoint(AdjKArgs a) {
+__global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_adjoint(AdjKArgs a) {
     using Sh = Shape<DIM, N>;
     using AL = AdjLayout<DIM, N>;
     using Pde = Acoustic<DIM>;
     constexpr int n = Sh::n, S = Sh::S, F = Sh::F, CPB = Sh::CPB, TPB = Sh::TPB, V = 1 + DIM;
     constexpr int NLP = AL::NLP;
     __shared__ __attribute__((aligned(16))) char smem[AL::bytes];
-    double *Xin = reinterpret_cast<double *>(smem);
-    double *Xout = Xin + n * NLP;
+    double *X = reinterpret_cast<double *>(smem);                                // [n][NLP]
     double *kred = reinterpret_cast<double *>(smem + AL::bytes - CPB * 8 * 4);  // per-cell partial sums
 
-    const DevBasis *B = a.B;
+    CBasis *B = (CBasis *)a.B;
     const int tid = threadIdx.x;
     const int cb = tid / S, s = tid % S;
     const long blk = xcd_block(blockIdx.x, gridDim.x);
@@ -118,17 +124,20 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) void k_adjoint(AdjKArgs a) {
     const typename Pde::Coef coef = Pde::cell(a.pde, active ? cell : 0);
     const double rho = a.pde.prm[0];
     const double K = coef.K, irho = coef.irho;
+    const double h = 1.0 / a.inv_h;
     const bool src_here = active && cell == a.src_cell;
     const double src_phi = src_here ? a.src_phi[s] : 0.0;
+    const int iters = a.iters;
 
-    // offsets of this node on the lines of each direction (variable 0)
+    // offset of this node on its line of each direction (slot 0)
     int po[DIM], pi[DIM], pf[DIM];
 #pragma unroll
     for (int j = 0; j < DIM; j++) {
         pi[j] = coord<n>(s, j);
         pf[j] = face_of<n, DIM>(s, j);
-        po[j] = pi[j] * NLP + ((cb * DIM + j) * 2 * V) * F + pf[j];
+        po[j] = pi[j] * NLP + ((cb * DIM + j) * AL::NZ) * F + pf[j];
     }
+    constexpr int NHALF = CPB * DIM * 2 * F;  // slot 0/1 lines
 
     double Qn[V], lam[V];
 #pragma unroll
@@ -139,87 +148,98 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) void k_adjoint(AdjKArgs a) {
     if (tid < CPB * 4) kred[tid] = 0.0;
 
     // ---- forward Picard with its K-tangent ----
-    double q[n][V], qd[n][V], acc[n][V], accd[n][V];
+    // z[t] (zd[t]): the iterate (its K-derivative) at time node t; during an
+    // iteration row b is reused for h R_b (h dR_b/dK) once slice b is done, and
+    // after the last slice all rows become q_a = Q - sigma sum_b Atau[a][b] h R_b.
+    // First iteration: all slices equal (Q, 0), one divergence serves them all.
+    double z[n][V], zd[n][V];
 #pragma unroll
     for (int t = 0; t < n; t++)
 #pragma unroll
         for (int v = 0; v < V; v++) {
-            q[t][v] = Qn[v];
-            qd[t][v] = 0.0;
+            z[t][v] = Qn[v];
+            zd[t][v] = 0.0;
         }
+    auto src_term = [&](int b) { return h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi; };
 #pragma unroll 1
-    for (int it = 0; it < a.iters; it++) {
+    for (int it = 0; it < iters; it++) {
 #pragma unroll
-        for (int t = 0; t < n; t++)
-#pragma unroll
-            for (int v = 0; v < V; v++) {
-                acc[t][v] = 0.0;
-                accd[t][v] = 0.0;
-            }
-#pragma unroll 1
         for (int b = 0; b < n; b++) {
-            double qb[V], qdb[V];
-#pragma unroll
-            for (int v = 0; v < V; v++) {
-                qb[v] = q[0][v];
-                qdb[v] = qd[0][v];
-            }
-#pragma unroll
-            for (int t = 1; t < n; t++)
-                if (t == b) {
-#pragma unroll
-                    for (int v = 0; v < V; v++) {
-                        qb[v] = q[t][v];
-                        qdb[v] = qd[t][v];
-                    }
-                }
+            if (it == 0 && b > 0) continue;
             if (slot) {
 #pragma unroll
                 for (int j = 0; j < DIM; j++) {
-                    double Fv[V], Fd[V];
-                    Pde::flux(coef, qb, j, Fv);
-                    Pde::flux(coef, qdb, j, Fd);
-                    Fd[0] += qb[1 + j];  // dF_j/dK
-#pragma unroll
-                    for (int v = 0; v < V; v++) {
-                        Xin[po[j] + v * F] = active ? Fv[v] : 0.0;
-                        Xin[po[j] + (V + v) * F] = active ? Fd[v] : 0.0;
-                    }
+                    const double vj = z[b][1 + j], p = z[b][0], vdj = zd[b][1 + j], pd = zd[b][0];
+                    X[po[j] + 0 * F] = active ? K * vj : 0.0;
+                    X[po[j] + 1 * F] = active ? p * irho : 0.0;
+                    X[po[j] + 2 * F] = active ? K * vdj + vj : 0.0;  // d(K v_j)/dK
+                    X[po[j] + 3 * F] = active ? pd * irho : 0.0;
                 }
             }
             __syncthreads();
-            lines_pm<n, false>(Xin, Xout, AL::NL, NLP, B->D, tid, TPB);
+            lines_inplace<n, false>(X, AL::NL, NLP, B->D, [](int L) { return L; }, tid, TPB);
             __syncthreads();
             if (active) {
-                double R[V], Rd[V];
+                double r[V], rd[V];
+                r[0] = 0.0;
+                rd[0] = 0.0;
 #pragma unroll
-                for (int v = 0; v < V; v++) {
-                    double r = 0.0, rd = 0.0;
-#pragma unroll
-                    for (int j = 0; j < DIM; j++) {
-                        r += Xout[po[j] + v * F];
-                        rd += Xout[po[j] + (V + v) * F];
-                    }
-                    R[v] = r * a.inv_h;
-                    Rd[v] = rd * a.inv_h;
+                for (int j = 0; j < DIM; j++) {
+                    r[0] += X[po[j]];
+                    rd[0] += X[po[j] + 2 * F];
+                    r[1 + j] = X[po[j] + F];
+                    rd[1 + j] = X[po[j] + 3 * F];
                 }
-                if (src_here) R[0] -= ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
+                if (it == 0) {
 #pragma unroll
-                for (int t = 0; t < n; t++)
+                    for (int t = 0; t < n; t++) {
 #pragma unroll
-                    for (int v = 0; v < V; v++) {
-                        acc[t][v] = fma(B->Atau[t][b], R[v], acc[t][v]);
-                        accd[t][v] = fma(B->Atau[t][b], Rd[v], accd[t][v]);
+                        for (int v = 0; v < V; v++) {
+                            double acc = B->Arow[t] * r[v];
+                            if (v == 0 && src_here) {
+#pragma unroll
+                                for (int bb = 0; bb < n; bb++) acc = fma(B->Atau[t][bb], -src_term(bb), acc);
+                            }
+                            z[t][v] = fma(-a.sigma, acc, Qn[v]);
+                            zd[t][v] = -a.sigma * (B->Arow[t] * rd[v]);
+                        }
                     }
+                } else {
+                    if (src_here) r[0] -= src_term(b);
+#pragma unroll
+                    for (int t = 0; t < n; t++)
+                        if (t == b) {
+#pragma unroll
+                            for (int v = 0; v < V; v++) {
+                                z[t][v] = r[v];
+                                zd[t][v] = rd[v];
+                            }
+                        }
+                }
             }
         }
-#pragma unroll
-        for (int t = 0; t < n; t++)
+        if (it > 0 && active) {
 #pragma unroll
             for (int v = 0; v < V; v++) {
-                q[t][v] = fma(-a.dt, acc[t][v], Qn[v]);
-                qd[t][v] = -a.dt * accd[t][v];
+                double r[n], rd[n];
+#pragma unroll
+                for (int b = 0; b < n; b++) {
+                    r[b] = z[b][v];
+                    rd[b] = zd[b][v];
+                }
+#pragma unroll
+                for (int t = 0; t < n; t++) {
+                    double acc = 0.0, accd = 0.0;
+#pragma unroll
+                    for (int b = 0; b < n; b++) {
+                        acc = fma(B->Atau[t][b], r[b], acc);
+                        accd = fma(B->Atau[t][b], rd[b], accd);
+                    }
+                    z[t][v] = fma(-a.sigma, acc, Qn[v]);
+                    zd[t][v] = -a.sigma * accd;
+                }
             }
+        }
     }
     double qbar[V], qbard[V];
 #pragma unroll
@@ -228,15 +248,15 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) void k_adjoint(AdjKArgs a) {
         qbard[v] = 0.0;
 #pragma unroll
         for (int t = 0; t < n; t++) {
-            qbar[v] = fma(B->w[t], q[t][v], qbar[v]);
-            qbard[v] = fma(B->w[t], qd[t][v], qbard[v]);
+            qbar[v] = fma(B->w[t], z[t][v], qbar[v]);
+            qbard[v] = fma(B->w[t], zd[t][v], qbard[v]);
         }
     }
     __syncthreads();
 
     // ---- adjoint of the face integral and the Rusanov flux, per face node ----
-    double *gq = Xin;                                   // [cb][j][side][V][F]: adjoint of projected q
-    double *gf = Xin + (size_t)CPB * DIM * 2 * V * F;   // adjoint of projected F_j . e_j
+    double *gq = X;                                   // [cb][j][side][V][F]: adjoint of projected q
+    double *gf = X + (size_t)CPB * DIM * 2 * V * F;   // adjoint of projected F_j . e_j
     {
         constexpr int NRI = CPB * DIM * 2 * F;
         for (int itm = tid; itm < NRI; itm += TPB) {
@@ -270,13 +290,16 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) void k_adjoint(AdjKArgs a) {
         }
     }
     __syncthreads();
-    // expand the face adjoints into the cell (transpose of the projection)
-    double qbb[V], fbb[DIM][V];
+    // expand the face adjoints into the cell (transpose of the projection); of
+    // the flux adjoints only the components of F_j that are not identically
+    // zero (0 and 1+j) are needed
+    double qbb[V], fb0[DIM], fbj[DIM];
 #pragma unroll
-    for (int v = 0; v < V; v++) {
-        qbb[v] = 0.0;
+    for (int v = 0; v < V; v++) qbb[v] = 0.0;
 #pragma unroll
-        for (int j = 0; j < DIM; j++) fbb[j][v] = 0.0;
+    for (int j = 0; j < DIM; j++) {
+        fb0[j] = 0.0;
+        fbj[j] = 0.0;
     }
     if (active) {
 #pragma unroll
@@ -287,100 +310,114 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) void k_adjoint(AdjKArgs a) {
                 const int o0 = (((cb * DIM + j) * 2 + 0) * V + v) * F + pf[j];
                 const int o1 = (((cb * DIM + j) * 2 + 1) * V + v) * F + pf[j];
                 qbb[v] += e0 * gq[o0] + e1 * gq[o1];
-                fbb[j][v] += e0 * gf[o0] + e1 * gf[o1];
+                if (v == 0) fb0[j] += e0 * gf[o0] + e1 * gf[o1];
+                if (v == 1 + j) fbj[j] += e0 * gf[o0] + e1 * gf[o1];
             }
         }
     }
     __syncthreads();
-    // volume integral adjoint: fbar_j += sigma Kxi^T (x)_j lam
+    // volume integral adjoint: fbar_j += sigma Kxi^T (x)_j lam (components 0, 1+j)
     if (slot) {
 #pragma unroll
-        for (int j = 0; j < DIM; j++)
-#pragma unroll
-            for (int v = 0; v < V; v++) Xin[po[j] + v * F] = active ? lam[v] : 0.0;
+        for (int j = 0; j < DIM; j++) {
+            X[po[j]] = active ? lam[0] : 0.0;
+            X[po[j] + F] = active ? lam[1 + j] : 0.0;
+        }
     }
     __syncthreads();
-    lines_pm<n, true>(Xin, Xout, AL::NL, NLP, B->Kxi, tid, TPB);
+    lines_inplace<n, true>(X, NHALF, NLP, B->Kxi, [](int L) { return AL::half_line(L); }, tid, TPB);
     __syncthreads();
     double kpart = 0.0;
     if (active) {
 #pragma unroll
-        for (int j = 0; j < DIM; j++)
-#pragma unroll
-            for (int v = 0; v < V; v++) fbb[j][v] += a.sigma * Xout[po[j] + v * F];
+        for (int j = 0; j < DIM; j++) {
+            fb0[j] += a.sigma * X[po[j]];
+            fbj[j] += a.sigma * X[po[j] + F];
+        }
         // fbar_j = A_j qbar: qbar_adj += A_j^T fbar_adj, and dK through A_j
 #pragma unroll
         for (int j = 0; j < DIM; j++) {
-            qbb[0] += fbb[j][1 + j] * irho;
-            qbb[1 + j] += K * fbb[j][0];
-            kpart += fbb[j][0] * qbar[1 + j];
+            qbb[0] += fbj[j] * irho;
+            qbb[1 + j] += K * fb0[j];
+            kpart += fb0[j] * qbar[1 + j];
         }
 #pragma unroll
         for (int v = 0; v < V; v++) kpart += qbb[v] * qbard[v];
     }
 
     // ---- transposed Picard iterations ----
-    double mu[V];
-    double rh[n][V];  // adjoint of the current iterate, per time node
+    // rh[t]: adjoint of the iterate at time node t.  Each iteration first maps
+    // the rows to Rbar_b = -dt sum_a Atau[a][b] rh_a, then slice b's row is
+    // replaced by (1/h) sum_j D_j^T A_j^T Rbar_b once its lines are done.  First
+    // iteration: rh_a = w_a qbb, so Rbar_b = wA[b] (-dt qbb) and one line pass
+    // serves every slice.
+    double mu[V], rh[n][V];
 #pragma unroll
     for (int v = 0; v < V; v++) mu[v] = lam[v] + qbb[v];
-#pragma unroll
-    for (int t = 0; t < n; t++)
-#pragma unroll
-        for (int v = 0; v < V; v++) rh[t][v] = B->w[t] * qbb[v];
     __syncthreads();
 #pragma unroll 1
-    for (int it = 0; it < a.iters; it++) {
-        double rn[n][V];
-#pragma unroll
-        for (int t = 0; t < n; t++)
-#pragma unroll
-            for (int v = 0; v < V; v++) rn[t][v] = 0.0;
-#pragma unroll 1
-        for (int b = 0; b < n; b++) {
-            // Rbar_b = -dt sum_a Atau[a][b] rh_a, then A_j^T per direction
-            double Rb[V];
+    for (int it = 0; it < iters; it++) {
+        if (it > 0 && active) {
 #pragma unroll
             for (int v = 0; v < V; v++) {
-                double r = 0.0;
+                double tmp[n];
 #pragma unroll
-                for (int t = 0; t < n; t++) r = fma(B->Atau[t][b], rh[t][v], r);
-                Rb[v] = -a.dt * r;
+                for (int t = 0; t < n; t++) tmp[t] = rh[t][v];
+#pragma unroll
+                for (int b = 0; b < n; b++) {
+                    double r = 0.0;
+#pragma unroll
+                    for (int t = 0; t < n; t++) r = fma(B->Atau[t][b], tmp[t], r);
+                    rh[b][v] = -a.dt * r;
+                }
             }
+        }
+#pragma unroll
+        for (int b = 0; b < n; b++) {
+            if (it == 0 && b > 0) continue;
+            double Rb[V];
+#pragma unroll
+            for (int v = 0; v < V; v++) Rb[v] = it == 0 ? -a.dt * qbb[v] : rh[b][v];
             if (slot) {
 #pragma unroll
                 for (int j = 0; j < DIM; j++) {
-#pragma unroll
-                    for (int v = 0; v < V; v++) Xin[po[j] + v * F] = 0.0;
-                    Xin[po[j] + 0 * F] = active ? Rb[1 + j] * irho : 0.0;
-                    Xin[po[j] + (1 + j) * F] = active ? K * Rb[0] : 0.0;
+                    X[po[j]] = active ? Rb[1 + j] * irho : 0.0;
+                    X[po[j] + F] = active ? K * Rb[0] : 0.0;
                 }
             }
             __syncthreads();
-            lines_pm<n, true>(Xin, Xout, AL::NL, NLP, B->D, tid, TPB);
+            lines_inplace<n, true>(X, NHALF, NLP, B->D, [](int L) { return AL::half_line(L); }, tid, TPB);
             __syncthreads();
-            double nb_[V];
+            if (active) {
+                double nb_[V];
+                nb_[0] = 0.0;
 #pragma unroll
-            for (int v = 0; v < V; v++) {
-                double r = 0.0;
-                if (slot) {
-#pragma unroll
-                    for (int j = 0; j < DIM; j++) r += Xout[po[j] + v * F];
+                for (int j = 0; j < DIM; j++) {
+                    nb_[0] += X[po[j]];
+                    nb_[1 + j] = X[po[j] + F];
                 }
-                nb_[v] = r * a.inv_h;
-                mu[v] += nb_[v];
+#pragma unroll
+                for (int v = 0; v < V; v++) nb_[v] *= a.inv_h;
+                if (it == 0) {
+#pragma unroll
+                    for (int bb = 0; bb < n; bb++)
+#pragma unroll
+                        for (int v = 0; v < V; v++) {
+                            rh[bb][v] = B->wA[bb] * nb_[v];
+                            mu[v] += rh[bb][v];
+                        }
+                } else {
+#pragma unroll
+                    for (int v = 0; v < V; v++) mu[v] += nb_[v];
+#pragma unroll
+                    for (int t = 0; t < n; t++)
+                        if (t == b) {
+#pragma unroll
+                            for (int v = 0; v < V; v++) rh[t][v] = nb_[v];
+                        }
+                }
             }
-#pragma unroll
-            for (int t = 0; t < n; t++)
-                if (t == b) {
-#pragma unroll
-                    for (int v = 0; v < V; v++) rn[t][v] = nb_[v];
-                }
         }
-#pragma unroll
-        for (int t = 0; t < n; t++)
-#pragma unroll
-            for (int v = 0; v < V; v++) rh[t][v] = rn[t][v];
     }
 
     if (active) {

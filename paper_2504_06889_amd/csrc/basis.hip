@@ -209,6 +209,11 @@ bool build_basis(int n, DevBasis &B) {
         }
         B.Arow[k] = rs;
     }
+    for (int l = 0; l < n; l++) {
+        double cs = 0.0;
+        for (int k = 0; k < n; k++) cs += w[k] * A[k * n + l];
+        B.wA[l] = cs;
+    }
     for (int p = 0; p < 4; p++)
         for (int i = 0; i < n; i++) {
             B.F0p[p][i] = round_prec(p, B.F0[i]);

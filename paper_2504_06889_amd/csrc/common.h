@@ -37,6 +37,7 @@ struct DevBasis {
     double D[kMaxN][kMaxN];     // D[i][k] = psi_k'(xi_i)
     double Atau[kMaxN][kMaxN];  // Picard time operator K1^{-1} W
     double Arow[kMaxN];         // row sums sum_b Atau[a][b] (equal to xi_a)
+    double wA[kMaxN];           // weighted column sums sum_a w_a Atau[a][b]
     double Kxi[kMaxN][kMaxN];   // weak-form volume operator w_k' D[k'][k] / w_k
     double F0[kMaxN], F1[kMaxN];  // psi(0), psi(1)
     double L0[kMaxN], L1[kMaxN];  // face lifts psi(0)/w, psi(1)/w
