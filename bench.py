@@ -184,6 +184,79 @@ def adjoint_bench(steps=None, checkpoint=None, fd=True):
     return out
 
 
+def sweep_runs(pde):
+    """Precision settings (predictor, volume, flux) of the sweep: the 3-D Euler workload
+    varies one kernel at a time and all three together; shallow water runs FP32 and BF16
+    in the cell contractions (predictor and volume) and in every kernel."""
+    if pde == "swe":
+        return [("fp64", ("fp64",) * 3), ("predictor+volume=fp32", ("fp32", "fp32", "fp64")),
+                ("all=fp32", ("fp32",) * 3), ("predictor+volume=bf16", ("bf16", "bf16", "fp64")),
+                ("all=bf16", ("bf16",) * 3)]
+    runs = [("fp64", ("fp64",) * 3)]
+    for k, knob in enumerate(("predictor", "volume", "flux")):
+        for p in ("fp32", "bf16", "fp16"):
+            prec = ["fp64"] * 3
+            prec[k] = p
+            runs.append(("%s=%s" % (knob, p), tuple(prec)))
+    runs += [("all=%s" % p, (p,) * 3) for p in ("fp32", "bf16", "fp16")]
+    return runs
+
+
+def sweep():
+    """Per-kernel precision sweep on the 3-D Euler density wave (N=4, 48^3 cells, 200
+    steps) and the 2-D shallow-water bump (N=6, 512^2 cells, 500 steps): for every
+    setting the whole run's cell-DOF updates/s and the relative L2 error (eq. L2gauss)
+    of the final state against the FP64 GPU run (parity-checked against the oracle) and,
+    for Euler, against the exact solution."""
+    import torch
+    from paper_2504_06889_amd import inputs
+    from paper_2504_06889_amd.aderdg import NonFiniteError, Solver
+    out = {}
+    for name in ("euler3d_n4_48", "swe2d_n6_512"):
+        sc = inputs.SCENARIOS[name]
+        g = Solver.from_scenario(sc)
+        Q0 = torch.from_numpy(sc.initial_state(g.node_coords())).cuda()
+        g.set_state(Q0)
+        dt = g.max_dt(sc.cfl)
+        W = torch.from_numpy(g.weights()).cuda()
+        exact = None
+        if sc.ic == "euler_density_wave":
+            exact = torch.from_numpy(sc.initial_state(g.node_coords(), sc.steps * dt)).cuda()
+        dof = g.ncell * g.S * g.V
+        ref, runs = None, {}
+        for label, prec in sweep_runs(sc.pde):
+            g.set_precisions(*prec)
+            g.set_state(Q0)
+            g.time = 0.0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = {"precisions": dict(zip(("predictor", "volume", "flux"), prec))}
+            try:
+                g.step(dt, sc.steps)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                st = g.get_state(out=torch.empty(g.shape, dtype=torch.float64, device="cuda"))
+            except NonFiniteError as e:
+                r["error"] = "non-finite state: %s" % e
+                runs[label] = r
+                continue
+            if ref is None:
+                ref = st
+            nref = l2(W, g.h, g.d, ref)
+            r.update({"ms_per_step": 1e3 * el / sc.steps, "dof_per_s": dof * sc.steps / el,
+                      "l2_rel_vs_fp64_gpu": l2(W, g.h, g.d, st, ref) / nref})
+            if exact is not None:
+                r["l2_rel_vs_exact"] = l2(W, g.h, g.d, st, exact) / l2(W, g.h, g.d, exact)
+            runs[label] = r
+            print("%s %s: %s" % (name, label, ", ".join("%s %.4g" % (k, v) for k, v in r.items()
+                                                       if isinstance(v, float))), file=sys.stderr, flush=True)
+        out[name] = {"steps": sc.steps, "dt": dt, "cells": g.ncell, "order": sc.order, "runs": runs}
+        g.close()
+        del ref, Q0, exact
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +268,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only run the per-kernel precision sweep on the Euler and shallow-water workloads")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (3 times), to scale HBM counters")
     args = ap.parse_args()
@@ -218,6 +293,13 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
         return
     torch.cuda.set_device(0)
+    if args.sweep:
+        txt = json.dumps({"sweep": sweep()})
+        print(txt, flush=True)
+        if args.out:
+            with open(args.out, "w") as f:
+                f.write(txt + "\n")
+        return
     sc = inputs.SCENARIOS[args.workload]
     g = Solver.from_scenario(sc)
     print("workload %s: %d cells, N=%d, V=%d, S=%d" % (sc.name, g.ncell, sc.order, g.V, g.S), file=sys.stderr,

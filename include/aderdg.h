@@ -138,6 +138,20 @@ aderdg_status aderdg_read_receivers(aderdg_solver *s, double *out, int is_device
 aderdg_status aderdg_step_adjoint(aderdg_solver *s, double dt, double t, const double *Qn_dev,
                                   double *lam_dev, double *grad_dev);
 
+/* The face data of the last step's predictor (the time-averaged q and F_j
+ * projected to both sides of every face, Alg. 1 "expansion"), layout
+ * [cell][dir][side][q|f][var][face node] in the FLUX format, info[7] bytes per
+ * cell, copied to dst (device if is_device, else host; a host copy
+ * synchronises).  Valid after aderdg_step; dst is owned by the caller.       */
+aderdg_status aderdg_copy_faces(aderdg_solver *s, void *dst, int is_device);
+
+/* aderdg_step_adjoint with the forward face data of the step supplied by the
+ * caller (fwd_faces_dev: what aderdg_copy_faces returned right after the
+ * forward step from Qn, FLUX FP64) instead of recomputed from Qn: the result
+ * is identical, one predictor launch cheaper.  Errors as aderdg_step_adjoint. */
+aderdg_status aderdg_step_adjoint_faces(aderdg_solver *s, double dt, double t, const double *Qn_dev,
+                                        const void *fwd_faces_dev, double *lam_dev, double *grad_dev);
+
 /* Scatter the receiver misfit gradient: lam[cell][0][node] += sum_r
  * weight[r] * phi_node(x_r) over receivers in that cell (device pointers). */
 aderdg_status aderdg_receivers_adjoint(aderdg_solver *s, const double *weight_dev, double *lam_dev);

@@ -40,7 +40,7 @@ EXPORTS = [
     "aderdg_set_precision", "aderdg_max_dt", "aderdg_step", "aderdg_set_time", "aderdg_get_time",
     "aderdg_set_source", "aderdg_set_receivers", "aderdg_read_receivers", "aderdg_step_adjoint",
     "aderdg_receivers_adjoint", "aderdg_nodes", "aderdg_info", "aderdg_state_ptr", "aderdg_last_error",
-    "aderdg_set_timing", "aderdg_get_timing",
+    "aderdg_set_timing", "aderdg_get_timing", "aderdg_copy_faces", "aderdg_step_adjoint_faces",
 ]
 
 _lib = None
@@ -77,6 +77,8 @@ def lib():
         "aderdg_last_error": [vp],
         "aderdg_set_timing": [vp, i],
         "aderdg_get_timing": [vp, dp],
+        "aderdg_copy_faces": [vp, vp, i],
+        "aderdg_step_adjoint_faces": [vp, d, d, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -255,13 +257,33 @@ class Solver:
         return r
 
     # -- adjoint ------------------------------------------------------------------
-    def step_adjoint(self, dt, t, Qn, lam, grad):
-        """lam <- (step Jacobian)^T lam, grad += d<lam, step(Qn)>/dc (device tensors)."""
+    def face_bytes(self):
+        """Bytes of the face buffer (all cells) in the current FLUX format."""
+        info = (ctypes.c_longlong * 8)()
+        lib().aderdg_info(self._h, info)
+        return int(info[7]) * self.ncell
+
+    def copy_faces(self, out):
+        """Copy the last step's face data into `out` (a CUDA uint8 tensor of face_bytes())."""
+        assert out.is_cuda and out.is_contiguous() and out.numel() * out.element_size() >= self.face_bytes()
+        self._check(lib().aderdg_copy_faces(self._h, ctypes.c_void_p(out.data_ptr()), 1))
+        return out
+
+    def step_adjoint(self, dt, t, Qn, lam, grad, fwd_faces=None):
+        """lam <- (step Jacobian)^T lam, grad += d<lam, step(Qn)>/dc (device tensors).
+        fwd_faces: the face data copied right after the forward step from Qn (else they
+        are recomputed from Qn)."""
         for x in (Qn, lam, grad):
             assert x.is_cuda and x.is_contiguous()
-        self._check(lib().aderdg_step_adjoint(self._h, float(dt), float(t), ctypes.c_void_p(Qn.data_ptr()),
-                                              ctypes.c_void_p(lam.data_ptr()),
-                                              ctypes.c_void_p(grad.data_ptr())))
+        if fwd_faces is None:
+            self._check(lib().aderdg_step_adjoint(self._h, float(dt), float(t), ctypes.c_void_p(Qn.data_ptr()),
+                                                  ctypes.c_void_p(lam.data_ptr()),
+                                                  ctypes.c_void_p(grad.data_ptr())))
+        else:
+            assert fwd_faces.is_cuda and fwd_faces.is_contiguous()
+            self._check(lib().aderdg_step_adjoint_faces(
+                self._h, float(dt), float(t), ctypes.c_void_p(Qn.data_ptr()), ctypes.c_void_p(fwd_faces.data_ptr()),
+                ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(grad.data_ptr())))
 
     def receivers_adjoint(self, weight, lam):
         self._check(lib().aderdg_receivers_adjoint(self._h, ctypes.c_void_p(weight.data_ptr()),

@@ -6,7 +6,9 @@ read at the receivers after each step.  The gradient is the discrete adjoint
 of the whole time loop: the library's adjoint step (transpose of the step in
 Q, plus the material derivative) swept backwards, with the receiver residuals
 injected at each step.  States are checkpointed every `checkpoint` steps in
-the forward run and each segment is recomputed once in the backward sweep.
+the forward run and each segment is recomputed once in the backward sweep; the
+recomputation also keeps each step's forward face data, which the adjoint step
+needs, instead of having it recomputed from the stored state.
 """
 import torch
 
@@ -51,18 +53,23 @@ class ReceiverMisfit(torch.autograd.Function):
         nseg = (nsteps + K - 1) // K
         for m in range(nseg - 1, -1, -1):
             start, end = m * K, min((m + 1) * K, nsteps)
-            # recompute the states start .. end-1 of this segment
-            states = [ctx.ckpts[start]]
+            # recompute the states start .. end-1 of this segment and the face data of
+            # the steps start+1 .. end
+            states, faces = [ctx.ckpts[start]], []
             solver.set_state(ctx.ckpts[start])
             solver.time = t0 + start * dt
-            for k in range(start, end - 1):
+            nbytes = solver.face_bytes()
+            for k in range(start, end):
                 solver.step(dt, 1)
-                states.append(solver.get_state(out=torch.empty_like(Q0)))
+                faces.append(solver.copy_faces(torch.empty(nbytes, dtype=torch.uint8, device=Q0.device)))
+                if k < end - 1:
+                    states.append(solver.get_state(out=torch.empty_like(Q0)))
             for k in range(end, start, -1):
                 # misfit at t^k (state after step k), then the adjoint of step k
                 solver.receivers_adjoint(resid[k - 1].contiguous(), lam)
-                solver.step_adjoint(dt, t0 + (k - 1) * dt, states[k - 1 - start], lam, grad)
-            del states
+                solver.step_adjoint(dt, t0 + (k - 1) * dt, states[k - 1 - start], lam, grad,
+                                    fwd_faces=faces[k - 1 - start])
+            del states, faces
         ctx.adjoint_Q0 = lam
         return gJ * grad, None, None, None, None, None, None, None
 

@@ -17,6 +17,7 @@ struct AdjointArgs {
     double dt, t, inv_h, sigma;
     int iters;
     const double *Qn;
+    const void *fwdface;  // forward face data of the step, or null: recomputed from Qn
     double *lam;
     double *grad;
     long src_cell;

@@ -82,42 +82,45 @@ int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::stri
     int F = 1;
     for (int i = 1; i < a.dim; i++) F *= a.order + 1;
     const size_t lf = sizeof(double) * a.ncell * a.dim * 2 * V * F;
-    if (ensure(&w.lamface, &w.bytes_lamface, lf) || ensure(&w.fwdface, &w.bytes_fwdface, 2 * lf)) {
+    if (ensure(&w.lamface, &w.bytes_lamface, lf) || (!a.fwdface && ensure(&w.fwdface, &w.bytes_fwdface, 2 * lf))) {
         msg = "adjoint work allocation failed";
         return ADERDG_E_OOM;
     }
     // 1. face restrictions of the incoming adjoint
     it->second.first(a.lam, (double *)w.lamface, a.ncell, a.B, st);
-    // 2. forward face data of this step
-    StepArgs f;
-    f.Q = const_cast<double *>(a.Qn);
-    f.faces = w.fwdface;
-    f.B = a.B;
-    f.pde = a.pde;
-    f.ncell = a.ncell;
-    for (int i = 0; i < 3; i++) f.cells[i] = a.cells[i];
-    f.dt = a.dt;
-    f.inv_h = a.inv_h;
-    f.sigma = a.sigma;
-    f.t = a.t;
-    f.h = 1.0 / a.inv_h;
-    f.vol_prec = 0;
-    f.flux_prec = 0;
-    f.iters = a.iters;
-    f.write_state = 0;
-    f.src_cell = a.src_cell;
-    f.src_phi = a.src_phi;
-    f.src_f0 = a.src_f0;
-    f.src_t0 = a.src_t0;
-    f.src_amp = a.src_amp;
-    a.pred(f, st);
+    // 2. forward face data of this step (unless the caller kept them)
+    const void *fwd = a.fwdface ? a.fwdface : w.fwdface;
+    if (!a.fwdface) {
+        StepArgs f;
+        f.Q = const_cast<double *>(a.Qn);
+        f.faces = w.fwdface;
+        f.B = a.B;
+        f.pde = a.pde;
+        f.ncell = a.ncell;
+        for (int i = 0; i < 3; i++) f.cells[i] = a.cells[i];
+        f.dt = a.dt;
+        f.inv_h = a.inv_h;
+        f.sigma = a.sigma;
+        f.t = a.t;
+        f.h = 1.0 / a.inv_h;
+        f.vol_prec = 0;
+        f.flux_prec = 0;
+        f.iters = a.iters;
+        f.write_state = 0;
+        f.src_cell = a.src_cell;
+        f.src_phi = a.src_phi;
+        f.src_f0 = a.src_f0;
+        f.src_t0 = a.src_t0;
+        f.src_amp = a.src_amp;
+        a.pred(f, st);
+    }
     // 3. the adjoint proper
     AdjKArgs k;
     k.Qn = a.Qn;
     k.lam = a.lam;
     k.grad = a.grad;
     k.lamface = (const double *)w.lamface;
-    k.fwdface = (const double *)w.fwdface;
+    k.fwdface = (const double *)fwd;
     k.B = a.B;
     k.pde = a.pde;
     k.ncell = a.ncell;

@@ -97,7 +97,11 @@ struct AdjLayout {
     static constexpr int NLP = Fp64Pitch<n, DIM, NZ, CPB, Sh::TPB>::value;
     static constexpr size_t picard = (size_t)n * NLP * 8;
     static constexpr size_t faces = (size_t)2 * CPB * DIM * 2 * V * F * 8;  // q- and f-face adjoints
-    static constexpr size_t bytes = (picard > faces ? picard : faces) + (size_t)CPB * 8 * 4;
+    // per-cell material-derivative terms, summed in a fixed order: one per face
+    // node side (Rusanov speed) and one per thread (the rest)
+    static constexpr int NRI = CPB * DIM * 2 * F;
+    static constexpr size_t red = (size_t)(NRI + Sh::TPB) * 8;
+    static constexpr size_t bytes = (picard > faces ? picard : faces) + red;
     // line of the L-th slot-0/1 line (L < CPB*DIM*2*F)
     __device__ static int half_line(int L) { return (L / (2 * F)) * (NZ * F) + L % (2 * F); }
 };
@@ -111,7 +115,8 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
     constexpr int NLP = AL::NLP;
     __shared__ __attribute__((aligned(16))) char smem[AL::bytes];
     double *X = reinterpret_cast<double *>(smem);                                // [n][NLP]
-    double *kred = reinterpret_cast<double *>(smem + AL::bytes - CPB * 8 * 4);  // per-cell partial sums
+    double *fbuf = reinterpret_cast<double *>(smem + AL::bytes - AL::red);  // [NRI] Rusanov-speed terms
+    double *kbuf = fbuf + AL::NRI;                                           // [TPB] per-thread terms
 
     CBasis *B = (CBasis *)a.B;
     const int tid = threadIdx.x;
@@ -145,7 +150,6 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
         Qn[v] = active ? a.Qn[(cell * V + v) * S + s] : 0.0;
         lam[v] = active ? a.lam[(cell * V + v) * S + s] : 0.0;
     }
-    if (tid < CPB * 4) kred[tid] = 0.0;
 
     // ---- forward Picard with its K-tangent ----
     // z[t] (zd[t]): the iterate (its K-derivative) at time node t; during an
@@ -258,8 +262,9 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
     double *gq = X;                                   // [cb][j][side][V][F]: adjoint of projected q
     double *gf = X + (size_t)CPB * DIM * 2 * V * F;   // adjoint of projected F_j . e_j
     {
-        constexpr int NRI = CPB * DIM * 2 * F;
+        constexpr int NRI = AL::NRI;
         for (int itm = tid; itm < NRI; itm += TPB) {
+            fbuf[itm] = 0.0;
             const int f = itm % F;
             int rr = itm / F;
             const int side = rr % 2;
@@ -286,7 +291,7 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
                 gq[o] = (side ? 0.5 : -0.5) * sp * G;
                 gf[o] = 0.5 * G;
             }
-            if (c_is_max) atomicAdd(&kred[cbi], sbar / (2.0 * rho * a.pde.mat[c]));
+            if (c_is_max) fbuf[itm] = sbar / (2.0 * rho * a.pde.mat[c]);
         }
     }
     __syncthreads();
@@ -424,13 +429,23 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
 #pragma unroll
         for (int v = 0; v < V; v++) a.lam[(cell * V + v) * S + s] = mu[v];
     }
-    // dJ/dc = dJ/dK * dK/dc, reduced over the cell's threads
+    // dJ/dc = dJ/dK * dK/dc: each cell's terms summed by one wavefront in a
+    // fixed order (strided lane sums, then a butterfly), so the gradient is
+    // reproducible bit for bit
+    kbuf[tid] = active ? kpart : 0.0;
     __syncthreads();
-    if (active) atomicAdd(&kred[cb], kpart);
-    __syncthreads();
-    if (slot && s == 0 && active) {
-        const double c = a.pde.mat[cell];
-        a.grad[cell] += kred[cb] * 2.0 * rho * c;
+    {
+        const int lane = tid & 63, wave = tid >> 6;
+        constexpr int FPC = DIM * 2 * F;  // face terms per cell
+        for (int cr = wave; cr < CPB; cr += TPB / 64) {
+            double acc = 0.0;
+            for (int i = lane; i < FPC; i += 64) acc += fbuf[cr * FPC + i];
+            for (int i = lane; i < S; i += 64) acc += kbuf[cr * S + i];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            const long c = cell0 + cr;
+            if (lane == 0 && c < a.ncell) a.grad[c] += acc * 2.0 * rho * a.pde.mat[c];
+        }
     }
 }
 

@@ -491,8 +491,8 @@ aderdg_status aderdg_read_receivers(aderdg_solver *s, double *out, int is_device
     return ADERDG_OK;
 }
 
-aderdg_status aderdg_step_adjoint(aderdg_solver *s, double dt, double t, const double *Qn_dev, double *lam_dev,
-                                  double *grad_dev) {
+static aderdg_status step_adjoint(aderdg_solver *s, double dt, double t, const double *Qn_dev, const void *fwd,
+                                  double *lam_dev, double *grad_dev) {
     if (!s || !Qn_dev || !lam_dev || !grad_dev) return ADERDG_E_INVALID;
     if (!(dt > 0)) FAIL(s, ADERDG_E_INVALID, "dt must be positive");
     if (s->cfg.pde != ADERDG_ACOUSTIC || !s->dMat)
@@ -514,6 +514,7 @@ aderdg_status aderdg_step_adjoint(aderdg_solver *s, double dt, double t, const d
     a.sigma = dt / s->h;
     a.iters = s->iters;
     a.Qn = Qn_dev;
+    a.fwdface = fwd;
     a.lam = lam_dev;
     a.grad = grad_dev;
     a.src_cell = s->src_cell;
@@ -527,6 +528,28 @@ aderdg_status aderdg_step_adjoint(aderdg_solver *s, double dt, double t, const d
         s->err = msg;
         return (aderdg_status)rc;
     }
+    return ADERDG_OK;
+}
+
+aderdg_status aderdg_step_adjoint(aderdg_solver *s, double dt, double t, const double *Qn_dev, double *lam_dev,
+                                  double *grad_dev) {
+    return step_adjoint(s, dt, t, Qn_dev, nullptr, lam_dev, grad_dev);
+}
+
+aderdg_status aderdg_step_adjoint_faces(aderdg_solver *s, double dt, double t, const double *Qn_dev,
+                                        const void *fwd_faces_dev, double *lam_dev, double *grad_dev) {
+    if (!fwd_faces_dev) return ADERDG_E_INVALID;
+    return step_adjoint(s, dt, t, Qn_dev, fwd_faces_dev, lam_dev, grad_dev);
+}
+
+aderdg_status aderdg_copy_faces(aderdg_solver *s, void *dst, int is_device) {
+    if (!s || !dst) return ADERDG_E_INVALID;
+    long long info[8];
+    aderdg_info(s, info);
+    const size_t bytes = (size_t)info[7] * (size_t)s->ncell;
+    HIPC(s, hipMemcpyAsync(dst, s->dFaces, bytes, is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           s->stream));
+    if (!is_device) HIPC(s, hipStreamSynchronize(s->stream));
     return ADERDG_OK;
 }
 
