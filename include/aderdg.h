@@ -142,7 +142,9 @@ aderdg_status aderdg_step_adjoint(aderdg_solver *s, double dt, double t, const d
  * projected to both sides of every face, Alg. 1 "expansion"), layout
  * [cell][dir][side][q|f][var][face node] in the FLUX format, info[7] bytes per
  * cell, copied to dst (device if is_device, else host; a host copy
- * synchronises).  Valid after aderdg_step; dst is owned by the caller.       */
+ * synchronises).  For a linear PDE with FP64 faces the f half is not written
+ * (the corrector evaluates the flux from the projected q).  Valid after
+ * aderdg_step; dst is owned by the caller.                                  */
 aderdg_status aderdg_copy_faces(aderdg_solver *s, void *dst, int is_device);
 
 /* aderdg_step_adjoint with the forward face data of the step supplied by the

@@ -13,7 +13,8 @@
 //  k_corrector: per cell, the Rusanov flux on each face node of its 2d faces
 //    (eq. rusanov_flux; well-balanced form for shallow water) and the face
 //    integral (lift) into Q in FP64.
-//  Face buffer: faces[cell][dir][side][q|f][var][face node] in the FLUX format.
+//  Face buffer: faces[cell][dir][side][q|f][var][face node] in the FLUX format
+//  (the f half is left unwritten where the corrector evaluates the flux from q).
 #pragma once
 
 #include <type_traits>
@@ -398,6 +399,15 @@ struct PredOcc {
         (PredLds<Pde, DIM, N, PP>::bytes * 2 <= 160 * 1024 && Shape<DIM, N>::TPB <= 256) ? 2 : 1;
 };
 
+// For a linear flux with cell-constant coefficients and FP64 faces, the face
+// projection of Fbar_j = F_j(qbar) equals F_j of the projected qbar, so only
+// the projected qbar is stored and the corrector evaluates the flux from it
+// (half the face traffic).
+template <class Pde, int FP>
+struct FluxFromFaceState {
+    static constexpr bool value = Pde::kLinear && FP == P64;
+};
+
 // Projection of one line onto the face at side 0 (xi = 0) or 1 (xi = 1), as in
 // Alg. 1 "expansion": FP64, or inputs rounded to the FLUX format FP and FP32
 // accumulation; stored in the FLUX format.
@@ -769,7 +779,9 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
 #pragma unroll
                     for (int side = 0; side < 2; side++) {
                         project_store<FP, n>(a.faces, ((base + (side * 2 + 0) * V) + v) * (long)F + f, xq, B, side);
-                        project_store<FP, n>(a.faces, ((base + (side * 2 + 1) * V) + v) * (long)F + f, xf, B, side);
+                        if (!FluxFromFaceState<Pde, FP>::value)
+                            project_store<FP, n>(a.faces, ((base + (side * 2 + 1) * V) + v) * (long)F + f, xf, B,
+                                                 side);
                     }
                 }
                 if (vp == P64) {
@@ -861,14 +873,22 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) void k_corrector(StepArgs a) 
         CT qm[V], fm[V], qp[V], fp[V];
         const long bl = (((cl * DIM + j) * 2 + 1) * 2) * V * (long)F + f;
         const long br = (((cr * DIM + j) * 2 + 0) * 2) * V * (long)F + f;
+        const typename Pde::Coef kl = Pde::cell(a.pde, cl), kr = Pde::cell(a.pde, cr);
 #pragma unroll
         for (int v = 0; v < V; v++) {
             qm[v] = (CT)widen(faces[bl + (long)v * F]);
-            fm[v] = (CT)widen(faces[bl + (long)(V + v) * F]);
             qp[v] = (CT)widen(faces[br + (long)v * F]);
-            fp[v] = (CT)widen(faces[br + (long)(V + v) * F]);
         }
-        const typename Pde::Coef kl = Pde::cell(a.pde, cl), kr = Pde::cell(a.pde, cr);
+        if constexpr (FluxFromFaceState<Pde, FP>::value) {
+            flux_dir<Pde, DIM>(kl, qm, j, fm);
+            flux_dir<Pde, DIM>(kr, qp, j, fp);
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; v++) {
+                fm[v] = (CT)widen(faces[bl + (long)(V + v) * F]);
+                fp[v] = (CT)widen(faces[br + (long)(V + v) * F]);
+            }
+        }
         const CT sl = Pde::speed(kl, qm, j), sr = Pde::speed(kr, qp, j);
         const CT sp = sl > sr ? sl : sr;
         CT Gv[V], Dq[V];
