@@ -56,15 +56,30 @@ def predictor_flops(pde, d, N, V, I):
     return deriv + volume, time_op + adds + avg + faces, flux
 
 
-def predictor_bytes(d, N, V, face_bytes):
+def corrector_flops(d, N, V):
+    """Flops per cell of the corrector: Rusanov flux at the d*F nodes of each of the
+    2d faces (computed from both sides) and the lift into the S*V state values."""
     n = N + 1
     S = n ** d
     F = S // n
-    return 2 * S * V * 8 + 2 * d * 2 * V * F * face_bytes
+    return 2 * d * F * (6 * V + 20) + 4 * d * V * S
+
+
+def fused_bytes(d, N, V, face_bytes, q_only):
+    """HBM bytes per cell of one fused launch (corrector of the previous step +
+    predictor): Q* read and written (FP64), the previous face data of the cell and of
+    its neighbours read, the new face data written.  For a linear PDE with FP64 faces
+    only the projected q is stored."""
+    n = N + 1
+    S = n ** d
+    F = S // n
+    faces = 2 * d * V * F * face_bytes * (1 if q_only else 2)
+    return 2 * S * V * 8 + 2 * faces + faces
 
 
 # Sources that determine the machine code of k_predictor for this workload.
 KERNEL_SOURCES = ("paper_2504_06889_amd/csrc/common.h", "paper_2504_06889_amd/csrc/kernels.h",
+                  "paper_2504_06889_amd/csrc/registry.h",
                   "paper_2504_06889_amd/csrc/inst_elastic3.hip", "paper_2504_06889_amd/build.py")
 TRAFFIC_FILE = "profiles/k_predictor_elastic3d_n5_64_hbm_traffic.md"
 
@@ -331,17 +346,18 @@ def main():
         g.step(dt, args.steps)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        tp, tc, nt = g.get_timing()
+        tm = g.get_timing()
         g.set_timing(False)
         out = torch.empty(g.shape, dtype=torch.float64, device="cuda")
         g.get_state(out)
         states[p] = out
         runs[p] = {"precisions": {"predictor": prec[0], "volume": prec[1], "flux": prec[2]},
                    "ms_per_step": 1e3 * el / args.steps, "dof_per_s": dof * args.steps / el,
-                   "predictor_ms": tp / max(nt, 1), "corrector_ms": tc / max(nt, 1),
+                   "kernel_ms_per_step": (tm["predictor_ms"] + tm["corrector_ms"] + tm["fused_ms"]) / max(tm["steps"], 1),
+                   "fused_kernel_ms": tm["fused_ms"] / max(tm["fused_launches"], 1),
                    "l2_rel_vs_exact": l2(W, g.h, g.d, out, exact) / nexact}
-        print("%s: %.3f ms/step (predictor %.3f, corrector %.3f)" % (
-            p, runs[p]["ms_per_step"], runs[p]["predictor_ms"], runs[p]["corrector_ms"]), file=sys.stderr,
+        print("%s: %.3f ms/step (kernels %.3f ms/step, fused corrector+predictor kernel %.3f ms)" % (
+            p, runs[p]["ms_per_step"], runs[p]["kernel_ms_per_step"], runs[p]["fused_kernel_ms"]), file=sys.stderr,
             flush=True)
     if "fp64" in states:
         nref = l2(W, g.h, g.d, states["fp64"])
@@ -351,12 +367,13 @@ def main():
             runs[p]["within_tolerance"] = bool(runs[p]["l2_rel_vs_fp64_gpu"] <= TOL[p])
             runs[p]["speedup_vs_fp64"] = runs["fp64"]["ms_per_step"] / runs[p]["ms_per_step"]
 
-    # roofline of the dominant kernel (the predictor) for each variant
+    # roofline of the dominant kernel (the fused corrector + predictor) for each variant
     traffic = measured_traffic() if args.workload == "elastic3d_n5_64" else {}
     I = g.iters
     mf, v64, fl = predictor_flops(sc.pde, sc.dim, sc.order, g.V, I)
+    v64 += corrector_flops(sc.dim, sc.order, g.V)
     for p in runs:
-        t = runs[p]["predictor_ms"] * 1e-3
+        t = runs[p]["fused_kernel_ms"] * 1e-3
         total = (mf + v64 + fl) * g.ncell
         if p == "fp64":
             ideal = total / PEAK["fp64"]
@@ -366,7 +383,7 @@ def main():
             t_v = v64 * g.ncell / PEAK["fp64"] + fl * g.ncell / PEAK["fp32_valu"]
             ideal = t_m + t_v
             bound = "mfma" if t_m > t_v else "alu"
-        hbm = predictor_bytes(sc.dim, sc.order, g.V, 8) * g.ncell
+        hbm = fused_bytes(sc.dim, sc.order, g.V, 8, sc.pde in ("acoustic", "elastic")) * g.ncell
         runs[p]["roofline"] = {
             "bound": bound, "achieved": total / t / 1e12, "peak": total / ideal / 1e12, "unit": "TFLOP/s",
             "frac": ideal / t, "traffic": traffic.get(p),

@@ -168,10 +168,14 @@ aderdg_status aderdg_info(const aderdg_solver *s, long long *info);
 /* Device pointer of the state (for zero-copy use by the caller; stream-ordered). */
 aderdg_status aderdg_state_ptr(aderdg_solver *s, double **dev_ptr);
 
-/* Kernel timing: when enabled, every predictor and corrector launch of
- * aderdg_step is bracketed by HIP events on the solver's stream.
- * aderdg_get_timing synchronises and returns out[0] = total predictor ms,
- * out[1] = total corrector ms, out[2] = number of steps timed, then resets. */
+/* Kernel timing: when enabled, every launch of aderdg_step is bracketed by
+ * HIP events on the solver's stream.  aderdg_step runs the predictor of its
+ * first step, one fused launch per later step (the corrector of the previous
+ * step and the predictor of this one) and the corrector of its last step.
+ * aderdg_get_timing synchronises and returns out[0] = total ms of the
+ * separate predictor launches, out[1] = of the separate corrector launches,
+ * out[2] = number of steps timed, out[3] = total ms of the fused launches,
+ * out[4] = number of fused launches; then resets.                           */
 aderdg_status aderdg_set_timing(aderdg_solver *s, int enable);
 aderdg_status aderdg_get_timing(aderdg_solver *s, double *out);
 

@@ -228,10 +228,13 @@ class Solver:
         self._check(lib().aderdg_set_timing(self._h, 1 if enable else 0))
 
     def get_timing(self):
-        """(predictor ms total, corrector ms total, steps) since timing was enabled."""
-        out = (ctypes.c_double * 3)()
+        """Kernel times since timing was enabled: total ms of the separate predictor and
+        corrector launches, of the fused (corrector + predictor) launches, their counts
+        and the number of steps."""
+        out = (ctypes.c_double * 5)()
         self._check(lib().aderdg_get_timing(self._h, out))
-        return out[0], out[1], int(out[2])
+        return {"predictor_ms": out[0], "corrector_ms": out[1], "steps": int(out[2]), "fused_ms": out[3],
+                "fused_launches": int(out[4])}
 
     # -- source and receivers ---------------------------------------------------
     def set_source(self, x, f0, t0, amp=1.0):

@@ -8,6 +8,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "aderdg.h"
@@ -78,7 +79,8 @@ struct aderdg_solver {
     DevBasis hB;
     DevBasis *dB = nullptr;
     double *dQ = nullptr;
-    void *dFaces = nullptr;
+    void *dFaces = nullptr;     // face data of the last predictor
+    void *dFaces2 = nullptr;    // second buffer: a fused step reads one and writes the other
     size_t face_elems = 0;
     double *dMat = nullptr;
     double *dSrcPhi = nullptr;
@@ -92,8 +94,9 @@ struct aderdg_solver {
     int prec[4] = {0, 0, 0, 0};
     AdjointWork adj;
     bool timing = false;
-    std::vector<hipEvent_t> ev;  // 3 events per timed step
-    int ev_used = 0;
+    std::vector<hipEvent_t> ev;  // 2 events per timed launch
+    std::vector<int> ev_kind;    // 0 predictor, 1 corrector, 2 fused corrector + predictor
+    int ev_used = 0, steps_timed = 0;
     std::string err;
 };
 
@@ -119,6 +122,7 @@ static void free_all(aderdg_solver *s) {
     hipFree(s->dB);
     hipFree(s->dQ);
     hipFree(s->dFaces);
+    hipFree(s->dFaces2);
     hipFree(s->dMat);
     hipFree(s->dSrcPhi);
     hipFree(s->dRecCell);
@@ -199,6 +203,7 @@ aderdg_status aderdg_create(const aderdg_config *cfg, void *hip_stream, aderdg_s
     e = hipMalloc(&s->dB, sizeof(DevBasis));
     if (e == hipSuccess) e = hipMalloc(&s->dQ, sizeof(double) * state_elems(s));
     if (e == hipSuccess) e = hipMalloc(&s->dFaces, sizeof(double) * s->face_elems);
+    if (e == hipSuccess) e = hipMalloc(&s->dFaces2, sizeof(double) * s->face_elems);
     if (e == hipSuccess) e = hipMalloc(&s->dScalar, sizeof(unsigned long long) * 4);
     if (e == hipSuccess) e = hipMalloc(&s->dFlag, sizeof(int) * 4);
     if (e != hipSuccess) {
@@ -315,6 +320,7 @@ static StepArgs step_args(aderdg_solver *s, double dt, double t) {
     StepArgs a;
     a.Q = s->dQ;
     a.faces = s->dFaces;
+    a.faces_in = nullptr;
     a.B = s->dB;
     a.pde = pde_args(s);
     a.ncell = s->ncell;
@@ -336,32 +342,54 @@ static StepArgs step_args(aderdg_solver *s, double dt, double t) {
     return a;
 }
 
+// Launch with optional timing events (kind: 0 predictor, 1 corrector, 2 fused).
+static aderdg_status launch(aderdg_solver *s, StepFn fn, const StepArgs &a, int kind) {
+    if (!s->timing) {
+        fn(a, s->stream);
+        return ADERDG_OK;
+    }
+    if ((size_t)(s->ev_used + 2) > s->ev.size()) {
+        for (int i = 0; i < 2 * 64; i++) {
+            hipEvent_t x;
+            HIPC(s, hipEventCreate(&x));
+            s->ev.push_back(x);
+            s->ev_kind.push_back(0);
+        }
+    }
+    hipEvent_t *e = &s->ev[s->ev_used];
+    s->ev_kind[s->ev_used] = kind;
+    s->ev_used += 2;
+    HIPC(s, hipEventRecord(e[0], s->stream));
+    fn(a, s->stream);
+    HIPC(s, hipEventRecord(e[1], s->stream));
+    return ADERDG_OK;
+}
+
+// nsteps steps of Alg. 1: the predictor of step 1, then for every later step
+// one fused launch (corrector of the previous step, kept in registers, and
+// the predictor of this step; the face data alternate between two buffers),
+// and the corrector of the last step.  Identical arithmetic to separate
+// predictor and corrector launches.
 aderdg_status aderdg_step(aderdg_solver *s, double dt, int nsteps) {
     if (!s) return ADERDG_E_INVALID;
     if (!(dt > 0) || nsteps < 0) FAIL(s, ADERDG_E_INVALID, "dt must be positive and nsteps >= 0");
+    if (nsteps == 0) return ADERDG_OK;
     const StepFn pred = s->ks->pred[s->prec[ADERDG_K_PREDICTOR]];
+    const StepFn fused = s->ks->fused[s->prec[ADERDG_K_PREDICTOR]];
     const StepFn corr = s->ks->corr[s->prec[ADERDG_K_FLUX]];
-    for (int k = 0; k < nsteps; k++) {
-        StepArgs a = step_args(s, dt, s->t + k * dt);
-        hipEvent_t *e = nullptr;
-        if (s->timing) {
-            if ((size_t)(s->ev_used + 3) > s->ev.size()) {
-                for (int i = 0; i < 3 * 64; i++) {
-                    hipEvent_t x;
-                    HIPC(s, hipEventCreate(&x));
-                    s->ev.push_back(x);
-                }
-            }
-            e = &s->ev[s->ev_used];
-            s->ev_used += 3;
-            HIPC(s, hipEventRecord(e[0], s->stream));
-        }
-        pred(a, s->stream);
-        if (e) HIPC(s, hipEventRecord(e[1], s->stream));
-        corr(a, s->stream);
-        if (e) HIPC(s, hipEventRecord(e[2], s->stream));
+    aderdg_status rc;
+    StepArgs a = step_args(s, dt, s->t);
+    if ((rc = launch(s, pred, a, 0)) != ADERDG_OK) return rc;
+    for (int k = 1; k < nsteps; k++) {
+        std::swap(s->dFaces, s->dFaces2);
+        a = step_args(s, dt, s->t + k * dt);
+        a.faces_in = s->dFaces2;
+        if ((rc = launch(s, fused, a, 2)) != ADERDG_OK) return rc;
     }
+    a = step_args(s, dt, s->t + (nsteps - 1) * dt);
+    if ((rc = launch(s, corr, a, 1)) != ADERDG_OK) return rc;
     HIPC(s, hipGetLastError());
+    if (s->timing) s->steps_timed += nsteps;
     s->t += nsteps * dt;
     return ADERDG_OK;
 }
@@ -370,24 +398,28 @@ aderdg_status aderdg_set_timing(aderdg_solver *s, int enable) {
     if (!s) return ADERDG_E_INVALID;
     s->timing = enable != 0;
     s->ev_used = 0;
+    s->steps_timed = 0;
     return ADERDG_OK;
 }
 
 aderdg_status aderdg_get_timing(aderdg_solver *s, double *out) {
     if (!s || !out) return ADERDG_E_INVALID;
     HIPC(s, hipStreamSynchronize(s->stream));
-    double tp = 0.0, tc = 0.0;
-    for (int i = 0; i + 2 < s->ev_used; i += 3) {
-        float a = 0.f, b = 0.f;
-        HIPC(s, hipEventElapsedTime(&a, s->ev[i], s->ev[i + 1]));
-        HIPC(s, hipEventElapsedTime(&b, s->ev[i + 1], s->ev[i + 2]));
-        tp += a;
-        tc += b;
+    double ms[3] = {0.0, 0.0, 0.0};
+    int cnt[3] = {0, 0, 0};
+    for (int i = 0; i + 1 < s->ev_used; i += 2) {
+        float x = 0.f;
+        HIPC(s, hipEventElapsedTime(&x, s->ev[i], s->ev[i + 1]));
+        ms[s->ev_kind[i]] += x;
+        cnt[s->ev_kind[i]]++;
     }
-    out[0] = tp;
-    out[1] = tc;
-    out[2] = s->ev_used / 3;
+    out[0] = ms[0];
+    out[1] = ms[1];
+    out[2] = s->steps_timed;
+    out[3] = ms[2];
+    out[4] = cnt[2];
     s->ev_used = 0;
+    s->steps_timed = 0;
     return ADERDG_OK;
 }
 

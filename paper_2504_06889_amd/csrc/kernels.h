@@ -25,7 +25,8 @@ namespace aderdg {
 
 struct StepArgs {
     double *Q;            // state [ncell][V][S]
-    void *faces;          // face buffer
+    void *faces;          // face buffer written by the predictor
+    const void *faces_in; // fused step: the previous step's face buffer (corrector input)
     const DevBasis *B;
     PdeArgs pde;
     long ncell;
@@ -388,7 +389,9 @@ struct PredLds {
     static constexpr size_t epi = EpiLayout<Pde, DIM, N>::bytes;
     static constexpr size_t ncp = Pde::kNCP ? (size_t)CPB * DIM * S * 8 : 0;
     static constexpr size_t bytes0 = picard > epi ? picard : epi;
-    static constexpr size_t bytes = bytes0 > ncp ? bytes0 : ncp;
+    static constexpr size_t bytes1 = bytes0 > ncp ? bytes0 : ncp;
+    static constexpr size_t corr = (size_t)Sh::CPB * DIM * 2 * V * Sh::F * 8;  // fused corrector
+    static constexpr size_t bytes = bytes1 > corr ? bytes1 : corr;
 };
 
 // Target occupancy of the predictor: two wavefronts per SIMD (at most 256
@@ -429,9 +432,132 @@ __device__ __forceinline__ void project_store(void *faces, long idx, const doubl
 template <int P> struct PrecC { static constexpr int value = P; };
 
 // ---------------------------------------------------------------------------
+// Corrector of the block's cells (Alg. 1, second traversal): the Rusanov flux
+// at every node of their 2d faces from `faces` (the cell's and its
+// neighbours' face data, FLUX format FP), into the LDS array G, then per node
+// the face integral (lift) added to Q*: qnew[v] = Q*[v] + sigma * lift.  The
+// caller stores qnew (k_corrector) or keeps it as the next step's state
+// (k_predictor, fused).  Threads of padding slots get qnew = 1.
+template <class Pde, int DIM, int N, int FP>
+__device__ __forceinline__ void correct_block(const StepArgs &a, const void *faces_v, char *smem, long cell0,
+                                              int tid, double *qnew) {
+    using Sh = Shape<DIM, N>;
+    constexpr int n = Sh::n, S = Sh::S, F = Sh::F, CPB = Sh::CPB, TPB = Sh::TPB, V = Pde::V;
+    using CT = typename std::conditional<FP == P64, double, float>::type;
+    using FT = typename FaceT<FP>::T;
+    CT *G = reinterpret_cast<CT *>(smem);  // [CPB][DIM][2][V][F]
+
+    const DevBasis *B = a.B;
+    const FT *faces = reinterpret_cast<const FT *>(faces_v);
+
+    constexpr int NRI = CPB * DIM * 2 * F;
+    for (int itm = tid; itm < NRI; itm += TPB) {
+        const int f = itm % F;
+        int rr = itm / F;
+        const int side = rr % 2;
+        rr /= 2;
+        const int j = rr % DIM;
+        const int cbi = rr / DIM;
+        const long c = cell0 + cbi;
+        if (c >= a.ncell) continue;
+        const long nb = neighbour(c, j, side ? 1 : -1, a.cells, DIM);
+        const long cl = side ? c : nb, cr = side ? nb : c;
+        CT qm[V], fm[V], qp[V], fp[V];
+        const long bl = (((cl * DIM + j) * 2 + 1) * 2) * V * (long)F + f;
+        const long br = (((cr * DIM + j) * 2 + 0) * 2) * V * (long)F + f;
+        const typename Pde::Coef kl = Pde::cell(a.pde, cl), kr = Pde::cell(a.pde, cr);
+#pragma unroll
+        for (int v = 0; v < V; v++) {
+            qm[v] = (CT)widen(faces[bl + (long)v * F]);
+            qp[v] = (CT)widen(faces[br + (long)v * F]);
+        }
+        if constexpr (FluxFromFaceState<Pde, FP>::value) {
+            flux_dir<Pde, DIM>(kl, qm, j, fm);
+            flux_dir<Pde, DIM>(kr, qp, j, fp);
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; v++) {
+                fm[v] = (CT)widen(faces[bl + (long)(V + v) * F]);
+                fp[v] = (CT)widen(faces[br + (long)(V + v) * F]);
+            }
+        }
+        const CT sl = Pde::speed(kl, qm, j), sr = Pde::speed(kr, qp, j);
+        const CT sp = sl > sr ? sl : sr;
+        CT Gv[V], Dq[V];
+#pragma unroll
+        for (int v = 0; v < V; v++) {
+            Gv[v] = (CT)0.5 * (fm[v] + fp[v]) - (CT)0.5 * sp * (qp[v] - qm[v]);
+            Dq[v] = (CT)0;
+        }
+        if constexpr (Pde::kNCP) {
+            const CT deta = (qp[0] + qp[3]) - (qm[0] + qm[3]);
+            Gv[0] = (CT)0.5 * (fm[0] + fp[0]) - (CT)0.5 * sp * deta;
+            Gv[3] = (CT)0.5 * (fm[3] + fp[3]);
+            Dq[1 + j] = (CT)0.5 * (CT)kl.g * (CT)0.5 * (qm[0] + qp[0]) * deta;
+        }
+#pragma unroll
+        for (int v = 0; v < V; v++) {
+            CT g = side ? Gv[v] + Dq[v] : Gv[v] - Dq[v];
+            if constexpr (FP != P64) g = widen(round_to<FP>(g));
+            G[(((cbi * DIM + j) * 2 + side) * V + v) * F + f] = g;
+        }
+    }
+    __syncthreads();
+
+    const int cb = tid / S, s = tid % S;
+    const long cell = cell0 + cb;
+    const bool active = cb < CPB && cell < a.ncell;
+#pragma unroll
+    for (int v = 0; v < V; v++) {
+        double dq = 0.0;
+        if (active) {
+#pragma unroll
+            for (int j = 0; j < DIM; j++) {
+                const int i = coord<n>(s, j);
+                const int f = face_of<n, DIM>(s, j);
+                const CT g0 = G[(((cb * DIM + j) * 2 + 0) * V + v) * F + f];
+                const CT g1 = G[(((cb * DIM + j) * 2 + 1) * V + v) * F + f];
+                if constexpr (FP == P64) {
+                    dq += B->L0[i] * g0 - B->L1[i] * g1;
+                } else {
+                    dq += (double)(B->L0p[FP][i] * g0) - (double)(B->L1p[FP][i] * g1);
+                }
+            }
+        }
+        qnew[v] = active ? fma(a.sigma, dq, a.Q[(cell * V + v) * S + s]) : 1.0;
+    }
+}
+
+template <class Pde, int DIM, int N>
+struct CorrLds {
+    static constexpr size_t bytes = (size_t)Shape<DIM, N>::CPB * DIM * 2 * Pde::V * Shape<DIM, N>::F * 8;
+};
+
+template <class Pde, int DIM, int N, int FP>
+__global__ __launch_bounds__((Shape<DIM, N>::TPB)) void k_corrector(StepArgs a) {
+    using Sh = Shape<DIM, N>;
+    constexpr int S = Sh::S, CPB = Sh::CPB, V = Pde::V;
+    __shared__ __attribute__((aligned(16))) char smem[CorrLds<Pde, DIM, N>::bytes];
+    const int tid = threadIdx.x;
+    const long cell0 = xcd_block(blockIdx.x, gridDim.x) * CPB;
+    double qnew[V];
+    correct_block<Pde, DIM, N, FP>(a, a.faces, smem, cell0, tid, qnew);
+    const int cb = tid / S, s = tid % S;
+    const long cell = cell0 + cb;
+    if (cb < CPB && cell < a.ncell) {
+#pragma unroll
+        for (int v = 0; v < V; v++) a.Q[(cell * V + v) * S + s] = qnew[v];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Predictor + face projection + volume integral (Alg. 1, first traversal)
 // ---------------------------------------------------------------------------
-template <class Pde, int DIM, int N, int PP>
+// FUSE: first the corrector of the previous step for the block's cells (from
+// a.faces_in and the Q* in a.Q), whose result is kept in registers as this
+// step's state: one launch per step, and the memory-bound corrector of one
+// workgroup overlaps the compute-bound predictor of another.
+template <class Pde, int DIM, int N, int PP, bool FUSE>
 __global__ __launch_bounds__((Shape<DIM, N>::TPB))
 __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_predictor(StepArgs a) {
     using Sh = Shape<DIM, N>;
@@ -451,8 +577,18 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     const typename Pde::Coef coef = Pde::cell(a.pde, active ? cell : 0);
 
     double Qn[V];
+    if constexpr (FUSE) {
+        switch (a.flux_prec) {
+        case P64: correct_block<Pde, DIM, N, P64>(a, a.faces_in, smem, cell0, tid, Qn); break;
+        case P32: correct_block<Pde, DIM, N, P32>(a, a.faces_in, smem, cell0, tid, Qn); break;
+        case PBF16: correct_block<Pde, DIM, N, PBF16>(a, a.faces_in, smem, cell0, tid, Qn); break;
+        default: correct_block<Pde, DIM, N, PF16>(a, a.faces_in, smem, cell0, tid, Qn); break;
+        }
+        __syncthreads();  // the LDS is reused below
+    } else {
 #pragma unroll
-    for (int v = 0; v < V; v++) Qn[v] = active ? a.Q[(cell * V + v) * S + s] : 1.0;
+        for (int v = 0; v < V; v++) Qn[v] = active ? a.Q[(cell * V + v) * S + s] : 1.0;
+    }
 
     const bool src_here = active && cell == a.src_cell;
     const double src_phi = src_here ? a.src_phi[s] : 0.0;
@@ -844,98 +980,6 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
 // Corrector: Riemann solve per face node and face integral (Alg. 1, second
 // traversal).  FP is the face format; FP32 arithmetic when FP != FP64.
 // ---------------------------------------------------------------------------
-template <class Pde, int DIM, int N, int FP>
-__global__ __launch_bounds__((Shape<DIM, N>::TPB)) void k_corrector(StepArgs a) {
-    using Sh = Shape<DIM, N>;
-    constexpr int n = Sh::n, S = Sh::S, F = Sh::F, CPB = Sh::CPB, TPB = Sh::TPB, V = Pde::V;
-    using CT = typename std::conditional<FP == P64, double, float>::type;
-    using FT = typename FaceT<FP>::T;
-    __shared__ CT G[CPB * DIM * 2 * V * F];
-
-    const DevBasis *B = a.B;
-    const FT *faces = reinterpret_cast<const FT *>(a.faces);
-    const int tid = threadIdx.x;
-    const long blk = xcd_block(blockIdx.x, gridDim.x);
-    const long cell0 = blk * CPB;
-
-    constexpr int NRI = CPB * DIM * 2 * F;
-    for (int itm = tid; itm < NRI; itm += TPB) {
-        const int f = itm % F;
-        int rr = itm / F;
-        const int side = rr % 2;
-        rr /= 2;
-        const int j = rr % DIM;
-        const int cbi = rr / DIM;
-        const long c = cell0 + cbi;
-        if (c >= a.ncell) continue;
-        const long nb = neighbour(c, j, side ? 1 : -1, a.cells, DIM);
-        const long cl = side ? c : nb, cr = side ? nb : c;
-        CT qm[V], fm[V], qp[V], fp[V];
-        const long bl = (((cl * DIM + j) * 2 + 1) * 2) * V * (long)F + f;
-        const long br = (((cr * DIM + j) * 2 + 0) * 2) * V * (long)F + f;
-        const typename Pde::Coef kl = Pde::cell(a.pde, cl), kr = Pde::cell(a.pde, cr);
-#pragma unroll
-        for (int v = 0; v < V; v++) {
-            qm[v] = (CT)widen(faces[bl + (long)v * F]);
-            qp[v] = (CT)widen(faces[br + (long)v * F]);
-        }
-        if constexpr (FluxFromFaceState<Pde, FP>::value) {
-            flux_dir<Pde, DIM>(kl, qm, j, fm);
-            flux_dir<Pde, DIM>(kr, qp, j, fp);
-        } else {
-#pragma unroll
-            for (int v = 0; v < V; v++) {
-                fm[v] = (CT)widen(faces[bl + (long)(V + v) * F]);
-                fp[v] = (CT)widen(faces[br + (long)(V + v) * F]);
-            }
-        }
-        const CT sl = Pde::speed(kl, qm, j), sr = Pde::speed(kr, qp, j);
-        const CT sp = sl > sr ? sl : sr;
-        CT Gv[V], Dq[V];
-#pragma unroll
-        for (int v = 0; v < V; v++) {
-            Gv[v] = (CT)0.5 * (fm[v] + fp[v]) - (CT)0.5 * sp * (qp[v] - qm[v]);
-            Dq[v] = (CT)0;
-        }
-        if constexpr (Pde::kNCP) {
-            const CT deta = (qp[0] + qp[3]) - (qm[0] + qm[3]);
-            Gv[0] = (CT)0.5 * (fm[0] + fp[0]) - (CT)0.5 * sp * deta;
-            Gv[3] = (CT)0.5 * (fm[3] + fp[3]);
-            Dq[1 + j] = (CT)0.5 * (CT)kl.g * (CT)0.5 * (qm[0] + qp[0]) * deta;
-        }
-#pragma unroll
-        for (int v = 0; v < V; v++) {
-            CT g = side ? Gv[v] + Dq[v] : Gv[v] - Dq[v];
-            if constexpr (FP != P64) g = widen(round_to<FP>(g));
-            G[(((cbi * DIM + j) * 2 + side) * V + v) * F + f] = g;
-        }
-    }
-    __syncthreads();
-
-    const int cb = tid / S, s = tid % S;
-    const long cell = cell0 + cb;
-    if (cb < CPB && cell < a.ncell) {
-#pragma unroll
-        for (int v = 0; v < V; v++) {
-            double dq = 0.0;
-#pragma unroll
-            for (int j = 0; j < DIM; j++) {
-                const int i = coord<n>(s, j);
-                const int f = face_of<n, DIM>(s, j);
-                const CT g0 = G[(((cb * DIM + j) * 2 + 0) * V + v) * F + f];
-                const CT g1 = G[(((cb * DIM + j) * 2 + 1) * V + v) * F + f];
-                if constexpr (FP == P64) {
-                    dq += B->L0[i] * g0 - B->L1[i] * g1;
-                } else {
-                    dq += (double)(B->L0p[FP][i] * g0) - (double)(B->L1p[FP][i] * g1);
-                }
-            }
-            double *qp_ = a.Q + (cell * V + v) * S + s;
-            *qp_ = fma(a.sigma, dq, *qp_);
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Largest wave speed over all nodes and directions (for eq. CFL_condition).
 // Non-negative doubles order like their bit patterns, so atomicMax on the

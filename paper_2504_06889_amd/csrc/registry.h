@@ -9,6 +9,7 @@ using MaxEigFn = void (*)(const double *, const PdeArgs &, long, unsigned long l
 
 struct KernelSet {
     StepFn pred[4] = {nullptr, nullptr, nullptr, nullptr};  // by predictor precision
+    StepFn fused[4] = {nullptr, nullptr, nullptr, nullptr}; // corrector of the previous step + predictor
     StepFn corr[4] = {nullptr, nullptr, nullptr, nullptr};  // by face (flux) precision
     MaxEigFn maxeig = nullptr;
     int V = 0, cpb = 0, tpb = 0;
@@ -23,7 +24,11 @@ struct Instance {
     static long grid(long ncell) { return (ncell + Sh::CPB - 1) / Sh::CPB; }
     template <int PP>
     static void pred(const StepArgs &a, hipStream_t st) {
-        hipLaunchKernelGGL((k_predictor<Pde, DIM, N, PP>), dim3(grid(a.ncell)), dim3(Sh::TPB), 0, st, a);
+        hipLaunchKernelGGL((k_predictor<Pde, DIM, N, PP, false>), dim3(grid(a.ncell)), dim3(Sh::TPB), 0, st, a);
+    }
+    template <int PP>
+    static void fused(const StepArgs &a, hipStream_t st) {
+        hipLaunchKernelGGL((k_predictor<Pde, DIM, N, PP, true>), dim3(grid(a.ncell)), dim3(Sh::TPB), 0, st, a);
     }
     template <int FP>
     static void corr(const StepArgs &a, hipStream_t st) {
@@ -38,10 +43,14 @@ struct Instance {
     Instance(int pde, bool mixed) {
         KernelSet ks;
         ks.pred[P64] = &pred<P64>;
+        ks.fused[P64] = &fused<P64>;
         if (mixed) {
             ks.pred[P32] = &pred<P32>;
             ks.pred[PBF16] = &pred<PBF16>;
             ks.pred[PF16] = &pred<PF16>;
+            ks.fused[P32] = &fused<P32>;
+            ks.fused[PBF16] = &fused<PBF16>;
+            ks.fused[PF16] = &fused<PF16>;
         }
         ks.corr[P64] = &corr<P64>;
         ks.corr[P32] = &corr<P32>;
