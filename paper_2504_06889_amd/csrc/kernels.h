@@ -449,6 +449,14 @@ __device__ __forceinline__ void correct_block(const StepArgs &a, const void *fac
 
     const DevBasis *B = a.B;
     const FT *faces = reinterpret_cast<const FT *>(faces_v);
+    // this thread's node values of Q*, loaded first so that their latency
+    // overlaps the Riemann solves
+    const int cb = tid / S, s = tid % S;
+    const long cell = cell0 + cb;
+    const bool active = cb < CPB && cell < a.ncell;
+    double qs[V];
+#pragma unroll
+    for (int v = 0; v < V; v++) qs[v] = active ? a.Q[(cell * V + v) * S + s] : 1.0;
 
     constexpr int NRI = CPB * DIM * 2 * F;
     for (int itm = tid; itm < NRI; itm += TPB) {
@@ -504,9 +512,6 @@ __device__ __forceinline__ void correct_block(const StepArgs &a, const void *fac
     }
     __syncthreads();
 
-    const int cb = tid / S, s = tid % S;
-    const long cell = cell0 + cb;
-    const bool active = cb < CPB && cell < a.ncell;
 #pragma unroll
     for (int v = 0; v < V; v++) {
         double dq = 0.0;
@@ -524,7 +529,7 @@ __device__ __forceinline__ void correct_block(const StepArgs &a, const void *fac
                 }
             }
         }
-        qnew[v] = active ? fma(a.sigma, dq, a.Q[(cell * V + v) * S + s]) : 1.0;
+        qnew[v] = active ? fma(a.sigma, dq, qs[v]) : 1.0;
     }
 }
 
