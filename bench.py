@@ -85,10 +85,16 @@ TRAFFIC_FILE = "profiles/k_predictor_elastic3d_n5_64_hbm_traffic.md"
 
 
 def kernel_source_hash():
+    """SHA-256 of the kernel sources with comments and blank lines removed (an edit
+    of a comment does not change the kernel)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0] if not f.endswith(".py") else line.split("#", 1)[0]
+                code = code.strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 

@@ -1,15 +1,16 @@
 // HIP kernels of the ADER-DG time step (arXiv 2504.06889, Alg. 1) for gfx950.
 //
 //  k_predictor: one workgroup per CPB cells, one thread per spatial node.
-//    Each thread keeps its node's space-time column q[a][v] (all time nodes,
-//    all variables) in registers.  Per Picard iteration and time slice b the
+//    Each thread keeps its node's space-time column (all time nodes, all
+//    variables) in registers.  Per Picard iteration and time slice b the
 //    pointwise fluxes F_j(q_b) are written to LDS, every 1-D line is
 //    differentiated (D along x, y, z: in place in FP64 on the vector ALU, or
 //    on the matrix cores in FP32/BF16/FP16 with FP32 accumulation), and the
 //    owner thread folds the divergence into the FP64 Picard update
 //    q_a <- Q - dt sum_b Atau[a][b] R_b (eq. Picard at the nodes).  The
-//    epilogue forms the FP64 time averages, projects q and F_j to the 2d faces
-//    (Alg. 1 "expansion") and adds the volume integral to Q.
+//    epilogue forms the FP64 time averages, projects them to the 2d faces
+//    (Alg. 1 "expansion") and adds the volume integral to Q.  The fused
+//    variant first runs the previous step's corrector for its cells.
 //  k_corrector: per cell, the Rusanov flux on each face node of its 2d faces
 //    (eq. rusanov_flux; well-balanced form for shallow water) and the face
 //    integral (lift) into Q in FP64.
@@ -568,7 +569,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     using Sh = Shape<DIM, N>;
     using L = PredLds<Pde, DIM, N, PP>;
     constexpr int n = Sh::n, S = Sh::S, F = Sh::F, CPB = Sh::CPB, TPB = Sh::TPB;
-    constexpr int V = Pde::V, NV = L::NV;
+    constexpr int V = Pde::V;
     __shared__ __attribute__((aligned(16))) char smem[L::bytes];
 
     CBasis *B = (CBasis *)a.B;

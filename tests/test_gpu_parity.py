@@ -190,6 +190,29 @@ def test_deterministic_and_resumable(oracle_mod):
         np.testing.assert_array_equal(g2.get_state(), A)
 
 
+@pytest.mark.parametrize("name,prec", [("elastic3d_n5", ("fp64",) * 3), ("elastic3d_n5", ("fp16", "fp16", "fp64")),
+                                       ("euler3d_n4", ("bf16", "bf16", "bf16")), ("swe2d_n3", ("fp64",) * 3)])
+def test_fused_steps_match_single_steps(oracle_mod, name, prec):
+    """aderdg_step(dt, k) runs one fused corrector+predictor launch per step after the
+    first; k calls of aderdg_step(dt, 1) run separate predictor and corrector launches.
+    The states agree bit for bit."""
+    sc, _, noise = _case(name)
+    o = make_oracle(oracle_mod, sc, sc.cells)
+    Q0 = sc.initial_state(o.node_coords())
+    Q0 = Q0 + noise * max(np.abs(Q0).max(), 1.0) * np.random.default_rng(3).standard_normal(Q0.shape)
+    dt = 0.5 * o.max_dt(sc.cfl)
+    g = gpu_solver(sc, sc.cells, prec=prec)
+    g.set_state(Q0)
+    g.time = 0.0
+    g.step(dt, 3)
+    A = g.get_state()
+    g.set_state(Q0)
+    g.time = 0.0
+    for _ in range(3):
+        g.step(dt, 1)
+    np.testing.assert_array_equal(g.get_state(), A)
+
+
 def test_nonfinite_state_is_reported():
     from paper_2504_06889_amd.aderdg import NonFiniteError
     sc, _, _ = _case("acoustic2d_n2")
