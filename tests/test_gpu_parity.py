@@ -200,7 +200,9 @@ def test_fused_steps_match_single_steps(oracle_mod, name, prec):
     o = make_oracle(oracle_mod, sc, sc.cells)
     Q0 = sc.initial_state(o.node_coords())
     Q0 = Q0 + noise * max(np.abs(Q0).max(), 1.0) * np.random.default_rng(3).standard_normal(Q0.shape)
+    o.set_state(Q0)
     dt = 0.5 * o.max_dt(sc.cfl)
+    assert np.isfinite(dt) and dt > 0
     g = gpu_solver(sc, sc.cells, prec=prec)
     g.set_state(Q0)
     g.time = 0.0
