@@ -78,6 +78,19 @@ __device__ __forceinline__ double widen(double x) { return x; }
 // Face-value storage per FLUX precision
 template <int P> struct FaceT { using T = typename Store<P>::T; };
 
+// Component 1 + j of a state (the momentum in direction j) for a j that may be
+// known only at run time: a select among the values, so that no register
+// array is indexed dynamically.  The empty asm makes the three values opaque;
+// otherwise the select of three loads is folded into one load through a
+// computed index, which puts the array in scratch memory.
+template <int DIM, class T>
+__device__ __forceinline__ T mom(const T *q, int j) {
+    if (__builtin_constant_p(j)) return q[1 + j];
+    T a = q[1], b = q[2], c = q[DIM];
+    asm("" : "+v"(a), "+v"(b), "+v"(c));
+    return j == 0 ? a : ((DIM == 2 || j == 1) ? b : c);
+}
+
 // ---------------------------------------------------------------------------
 // Per-cell physical parameters
 // ---------------------------------------------------------------------------
@@ -183,8 +196,9 @@ struct Euler {  // conserved (rho, rho v, E), ideal gas
     template <class T>
     __device__ static void flux(const Coef &c, const T *q, int j, T *F) {
         const T p = pressure(c, q);
-        const T uj = q[1 + j] / q[0];
-        F[0] = q[1 + j];
+        const T mj = mom<DIM>(q, j);
+        const T uj = mj / q[0];
+        F[0] = mj;
 #pragma unroll
         for (int i = 0; i < DIM; i++) F[1 + i] = q[1 + i] * uj + (i == j ? p : (T)0);
         F[1 + DIM] = uj * (q[1 + DIM] + p);
@@ -192,7 +206,7 @@ struct Euler {  // conserved (rho, rho v, E), ideal gas
     template <class T>
     __device__ static T speed(const Coef &c, const T *q, int j) {
         const T p = pressure(c, q);
-        return fabs(q[1 + j] / q[0]) + sqrt((T)c.g * p / q[0]);
+        return fabs(mom<DIM>(q, j) / q[0]) + sqrt((T)c.g * p / q[0]);
     }
     __host__ __device__ static constexpr bool flux_nz(int, int) { return true; }
 };
@@ -205,15 +219,16 @@ struct Swe {  // (h, hu, hv, b); pressure term as non-conservative g h grad(h+b)
     __device__ static Coef cell(const PdeArgs &a, long) { return Coef{a.prm[0]}; }
     template <class T>
     __device__ static void flux(const Coef &, const T *q, int j, T *F) {
-        const T uj = q[1 + j] / q[0];
-        F[0] = q[1 + j];
+        const T mj = mom<2>(q, j);
+        const T uj = mj / q[0];
+        F[0] = mj;
         F[1] = q[1] * uj;
         F[2] = q[2] * uj;
         F[3] = (T)0;
     }
     template <class T>
     __device__ static T speed(const Coef &c, const T *q, int j) {
-        return fabs(q[1 + j] / q[0]) + sqrt((T)c.g * q[0]);
+        return fabs(mom<2>(q, j) / q[0]) + sqrt((T)c.g * q[0]);
     }
     // eta = h + b, whose reference derivative feeds the non-conservative term
     template <class T>

@@ -395,12 +395,16 @@ struct PredLds {
     static constexpr size_t bytes = bytes1 > corr ? bytes1 : corr;
 };
 
-// Target occupancy of the predictor: two wavefronts per SIMD (at most 256
-// registers per lane) whenever the LDS allows two workgroups per CU.
+// Target occupancy of the predictor (wavefronts per SIMD, one workgroup of at
+// most four wavefronts per CU per wavefront and SIMD): three (at most 168
+// registers per lane) for the lower-format paths, whose iterate rows are FP32,
+// when the LDS holds three workgroups per CU; else two (256 registers) when it
+// holds two.
 template <class Pde, int DIM, int N, int PP>
 struct PredOcc {
-    static constexpr int waves =
-        (PredLds<Pde, DIM, N, PP>::bytes * 2 <= 160 * 1024 && Shape<DIM, N>::TPB <= 256) ? 2 : 1;
+    static constexpr size_t lds = PredLds<Pde, DIM, N, PP>::bytes;
+    static constexpr bool fits = Shape<DIM, N>::TPB <= 256;
+    static constexpr int waves = !fits ? 1 : (PP != P64 && lds * 3 <= 160 * 1024) ? 3 : (lds * 2 <= 160 * 1024 ? 2 : 1);
 };
 
 // For a linear flux with cell-constant coefficients and FP64 faces, the face
@@ -642,10 +646,10 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     auto src_term = [&](int b) {
         return a.h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
     };
-    // fold h R_b (variable v, slice b) into the iterate rows
-    auto fold = [&](int it, int b, int v, double r) {
+    // fold h R_b (variable v, slice b) into the iterate rows; `last`: the
+    // first iteration is also the last one
+    auto fold = [&](int it, int b, int v, double r, bool last) __attribute__((always_inline)) {
         if (it == 0) {
-            const bool last = iters == 1;
 #pragma unroll
             for (int t = 0; t < n; t++) {
                 double acc = B->Arow[t] * r;
@@ -665,7 +669,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         }
     };
     // end of an iteration > 0: rows hold h R_b; replace them by the new iterate
-    auto update = [&](bool last) {
+    auto update = [&](bool last) __attribute__((always_inline)) {
 #pragma unroll
         for (int v = 0; v < V; v++) {
             double r[n];
@@ -732,7 +736,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                             if (v >= 1 && v <= DIM)
                                 r += coef.g * z[b][0] * X[po[v - 1] + PL::FS::index(v - 1, V) * PL::VSTRIDE];
                         }
-                        fold(it, b, v, r);
+                        fold(it, b, v, r, iters == 1);
                     }
                 }
             }
@@ -757,70 +761,81 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
             oo[j] = PL::G::out_off(po[j], k);
         }
         __syncthreads();
-#pragma unroll 1
-        for (int it = 0; it < iters; it++) {
+        // one slice: flux of q_b at every node, the derivative lines and the
+        // divergence at the node, whose FP64 value for variable v goes to
+        // sink(v, r) (descending v)
+        auto slice = [&](int b, auto &&sink) __attribute__((always_inline)) {
+            // the flux sees the FP32 rounding of the FP64 iterate
+            float qb[V];
 #pragma unroll
-            for (int b = 0; b < n; b++) {
-                if (it == 0 && b > 0) continue;
-                // the flux sees the FP32 rounding of the FP64 iterate
-                float qb[V];
+            for (int v = 0; v < V; v++) qb[v] = (float)z[b][v];  // exact when FR
+            if (slot) {
 #pragma unroll
-                for (int v = 0; v < V; v++) qb[v] = (float)z[b][v];  // exact when FR
-                if (slot) {
+                for (int j = 0; j < DIM; j++) {
+                    float Fv[V];
+                    Pde::flux(coef, qb, j, Fv);
+                    auto comp_val = [&](int c) -> float {
+                        return c < 0 ? 0.0f : (c == V ? ncp_value<Pde>(qb) : Fv[c < V ? c : 0]);
+                    };
 #pragma unroll
-                    for (int j = 0; j < DIM; j++) {
-                        float Fv[V];
-                        Pde::flux(coef, qb, j, Fv);
-                        auto comp_val = [&](int c) -> float {
-                            return c < 0 ? 0.0f : (c == V ? ncp_value<Pde>(qb) : Fv[c < V ? c : 0]);
-                        };
-#pragma unroll
-                        for (int p = 0; p < PL::NP; p++) {
-                            T *dst = Fb + io[j] + p * PL::PSTRIDE;
-                            const float f0 = comp_val(PL::FS::comp(j, 2 * p)), f1 = comp_val(PL::FS::comp(j, 2 * p + 1));
-                            if constexpr (PP == P32) {
-                                *reinterpret_cast<f32x2 *>(dst) = f32x2{f0, f1};
-                            } else {
-                                const uint32_t lo = __builtin_bit_cast(uint16_t, round_to<PP>(f0));
-                                const uint32_t hi = __builtin_bit_cast(uint16_t, round_to<PP>(f1));
-                                *reinterpret_cast<uint32_t *>(dst) = lo | (hi << 16);
-                            }
+                    for (int p = 0; p < PL::NP; p++) {
+                        T *dst = Fb + io[j] + p * PL::PSTRIDE;
+                        const float f0 = comp_val(PL::FS::comp(j, 2 * p)), f1 = comp_val(PL::FS::comp(j, 2 * p + 1));
+                        if constexpr (PP == P32) {
+                            *reinterpret_cast<f32x2 *>(dst) = f32x2{f0, f1};
+                        } else {
+                            const uint32_t lo = __builtin_bit_cast(uint16_t, round_to<PP>(f0));
+                            const uint32_t hi = __builtin_bit_cast(uint16_t, round_to<PP>(f1));
+                            *reinterpret_cast<uint32_t *>(dst) = lo | (hi << 16);
                         }
-                    }
-                }
-                __syncthreads();
-                mp.template run<PL::NTILE, NWAVE, F>(Fb, Rb, wave, lane);
-                __syncthreads();
-                if (active) {
-                    // the divergence sum over directions is part of the FP32
-                    // contraction
-                    float rf[V], eta[DIM];
-#pragma unroll
-                    for (int v = 0; v < V; v++) rf[v] = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < DIM; j++) {
-#pragma unroll
-                        for (int p = 0; p < PL::NP; p++) {
-                            const f32x2 r2 = *reinterpret_cast<const f32x2 *>(Rb + oo[j] + p * PL::POSTRIDE);
-#pragma unroll
-                            for (int h = 0; h < 2; h++) {
-                                const int c = PL::FS::comp(j, 2 * p + h);
-                                if (c >= 0 && c < V) rf[c < V ? c : 0] += r2[h];
-                                if (Pde::kNCP && c == V) eta[j] = r2[h];
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int v = V - 1; v >= 0; v--) {
-                        double rr = (double)rf[v];
-                        if constexpr (Pde::kNCP) {
-                            if (v >= 1 && v <= DIM) rr += (double)((float)coef.g * qb[0] * eta[v - 1]);
-                        }
-                        fold(it, b, v, rr);
                     }
                 }
             }
-            if (it > 0 && active) update(it == iters - 1);
+            __syncthreads();
+            mp.template run<PL::NTILE, NWAVE, F>(Fb, Rb, wave, lane);
+            __syncthreads();
+            if (active) {
+                // the divergence sum over directions is part of the FP32
+                // contraction
+                float rf[V], eta[DIM];
+#pragma unroll
+                for (int v = 0; v < V; v++) rf[v] = 0.0f;
+#pragma unroll
+                for (int j = 0; j < DIM; j++) {
+#pragma unroll
+                    for (int p = 0; p < PL::NP; p++) {
+                        const f32x2 r2 = *reinterpret_cast<const f32x2 *>(Rb + oo[j] + p * PL::POSTRIDE);
+#pragma unroll
+                        for (int h = 0; h < 2; h++) {
+                            const int c = PL::FS::comp(j, 2 * p + h);
+                            if (c >= 0 && c < V) rf[c < V ? c : 0] += r2[h];
+                            if (Pde::kNCP && c == V) eta[j] = r2[h];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int v = V - 1; v >= 0; v--) {
+                    double rr = (double)rf[v];
+                    if constexpr (Pde::kNCP) {
+                        if (v >= 1 && v <= DIM) rr += (double)((float)coef.g * qb[0] * eta[v - 1]);
+                    }
+                    sink(v, rr);
+                }
+            }
+        };
+        // The first and the last iteration are peeled off the loop, so that
+        // qbar, formed with the last iterate, is not carried through it.
+        if (iters == 1) {
+            slice(0, [&](int v, double r) __attribute__((always_inline)) { fold(0, 0, v, r, true); });
+        } else {
+            slice(0, [&](int v, double r) __attribute__((always_inline)) { fold(0, 0, v, r, false); });
+#pragma unroll 1
+            for (int it = 1; it < iters; it++) {
+#pragma unroll
+                for (int b = 0; b < n; b++) slice(b, [&](int v, double r) __attribute__((always_inline)) { fold(it, b, v, r, false); });
+                if (it < iters - 1 && active) update(false);
+            }
+            if (active) update(true);
         }
     }
     __syncthreads();
