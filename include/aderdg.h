@@ -64,7 +64,8 @@ typedef enum { ADERDG_FP64 = 0, ADERDG_FP32 = 1, ADERDG_BF16 = 2, ADERDG_FP16 = 
 typedef struct {
     int dim;          /* 2 or 3 (shallow water: 2)                                    */
     int order;        /* polynomial order N (n = N+1 nodes per dimension)             */
-    int cells[3];     /* cells per dimension (entries beyond dim ignored)             */
+    int cells[3];     /* cells per dimension (entries beyond dim ignored); the total
+                         is at most 2^31 - 1                                          */
     double lo[3];     /* domain lower corner                                          */
     double hi[3];     /* domain upper corner; cells must be cubes (equal h)           */
     int pde;          /* aderdg_pde                                                   */
@@ -75,7 +76,8 @@ typedef struct {
 /* Create a solver (Sec. 2 scheme on the given grid).  Builds the
  * Gauss-Legendre basis and operators on the host in FP64, allocates the state
  * (zero), face buffers and constants on the current HIP device.  `hip_stream`
- * is a hipStream_t (may be NULL).  Errors: INVALID (bad config or NULL out),
+ * is a hipStream_t (may be NULL).  Errors: INVALID (bad config, 2^31 or more
+ * cells, or NULL out),
  * UNSUPPORTED (order/PDE/dim not built), OOM, DEVICE.                        */
 aderdg_status aderdg_create(const aderdg_config *cfg, void *hip_stream, aderdg_solver **out);
 

@@ -178,6 +178,11 @@ aderdg_status aderdg_create(const aderdg_config *cfg, void *hip_stream, aderdg_s
         }
         s->ncell *= cfg->cells[i];
     }
+    if (s->ncell > 2147483647L) {
+        g_create_err = "at most 2^31 - 1 cells";
+        delete s;
+        return ADERDG_E_INVALID;
+    }
     s->h = (cfg->hi[0] - cfg->lo[0]) / cfg->cells[0];
     for (int i = 0; i < s->d; i++) {
         const double hi = (cfg->hi[i] - cfg->lo[i]) / cfg->cells[i];

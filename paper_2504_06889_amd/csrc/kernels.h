@@ -55,15 +55,22 @@ __device__ __forceinline__ double ricker(double t, double f0, double t0, double 
     return amp * (1.0 - 2.0 * a) * exp(-a);
 }
 
+// Periodic neighbour of a cell across its face in direction j (dir = +1 or
+// -1).  Cell counts are below 2^31 (checked when a solver is created), so the
+// index arithmetic is 32-bit.
 __device__ __forceinline__ long neighbour(long cell, int j, int dir, const int *cells, int dim) {
-    long c0 = cell % cells[0];
-    long rest = cell / cells[0];
-    long c1 = dim > 1 ? rest % cells[1] : 0;
-    long c2 = dim > 2 ? rest / cells[1] : 0;
-    if (j == 0) c0 = (c0 + dir + cells[0]) % cells[0];
-    if (j == 1) c1 = (c1 + dir + cells[1]) % cells[1];
-    if (j == 2) c2 = (c2 + dir + cells[2]) % cells[2];
-    return c0 + (long)cells[0] * (c1 + (long)cells[1] * c2);
+    const unsigned c = (unsigned)cell, n0 = (unsigned)cells[0], n1 = (unsigned)cells[1], n2 = (unsigned)cells[2];
+    unsigned x = c % n0, y = 0, z = 0;
+    if (dim > 1) {
+        const unsigned r = c / n0;
+        y = r % n1;
+        if (dim > 2) z = r / n1;
+    }
+    auto step = [dir](unsigned v, unsigned m) { return dir > 0 ? (v + 1 == m ? 0u : v + 1) : (v == 0 ? m - 1 : v - 1); };
+    if (j == 0) x = step(x, n0);
+    else if (j == 1) y = step(y, n1);
+    else z = step(z, n2);
+    return (long)(x + n0 * (y + n1 * z));
 }
 
 // ---------------------------------------------------------------------------
@@ -98,6 +105,16 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short i16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values rounded to nearest-even in a 16-bit format P and packed into
+// one 32-bit word, the first in the low half (one conversion instruction).
+template <int P>
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+    if constexpr (P == PF16) return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{lo, hi}, f16x2));
+    else return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{lo, hi}, bf16x2));
+}
 
 // ---------------------------------------------------------------------------
 // Matrix-core derivative of variable pairs, inputs in format P (FP32, BF16 or
@@ -251,6 +268,12 @@ struct FluxSupport {
         int c = 0;
         for (int u = 0; u < v; u++) c += nz(j, u) ? 1 : 0;
         return c;
+    }
+    // no direction before j has a nonzero F[v]: the divergence of v starts at j
+    __host__ __device__ static constexpr bool first(int j, int v) {
+        for (int u = 0; u < j; u++)
+            if (nz(u, v)) return false;
+        return true;
     }
     static constexpr bool same_count() {
         for (int j = 1; j < DIM; j++)
@@ -781,13 +804,8 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                     for (int p = 0; p < PL::NP; p++) {
                         T *dst = Fb + io[j] + p * PL::PSTRIDE;
                         const float f0 = comp_val(PL::FS::comp(j, 2 * p)), f1 = comp_val(PL::FS::comp(j, 2 * p + 1));
-                        if constexpr (PP == P32) {
-                            *reinterpret_cast<f32x2 *>(dst) = f32x2{f0, f1};
-                        } else {
-                            const uint32_t lo = __builtin_bit_cast(uint16_t, round_to<PP>(f0));
-                            const uint32_t hi = __builtin_bit_cast(uint16_t, round_to<PP>(f1));
-                            *reinterpret_cast<uint32_t *>(dst) = lo | (hi << 16);
-                        }
+                        if constexpr (PP == P32) *reinterpret_cast<f32x2 *>(dst) = f32x2{f0, f1};
+                        else *reinterpret_cast<uint32_t *>(dst) = pack2<PP>(f0, f1);
                     }
                 }
             }
@@ -808,7 +826,10 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
 #pragma unroll
                         for (int h = 0; h < 2; h++) {
                             const int c = PL::FS::comp(j, 2 * p + h);
-                            if (c >= 0 && c < V) rf[c < V ? c : 0] += r2[h];
+                            if (c >= 0 && c < V) {
+                                if (PL::FS::first(j, c)) rf[c < V ? c : 0] = r2[h];
+                                else rf[c < V ? c : 0] += r2[h];
+                            }
                             if (Pde::kNCP && c == V) eta[j] = r2[h];
                         }
                     }

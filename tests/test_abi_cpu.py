@@ -63,3 +63,22 @@ def test_binding_refuses_to_run_without_gpu(libpath):
     from paper_2504_06889_amd.aderdg import Solver
     with pytest.raises(RuntimeError):
         Solver(2, 3, (4, 4), (0, 0), (1, 1), "acoustic", (1.0, 1.0))
+
+
+@pytest.mark.parametrize("cells", [(2048, 1024, 1024), (4, 0, 4)])
+def test_create_validates_grid_before_touching_the_device(libpath, cells):
+    """Grids of 2^31 or more cells (the kernels index cells in 32 bits) and empty
+    dimensions are rejected with INVALID before any device call."""
+    import ctypes
+    from paper_2504_06889_amd import aderdg
+    c = aderdg._Config()
+    c.dim, c.order, c.pde = 3, 1, aderdg.PDE["elastic"]
+    for k in range(3):
+        c.cells[k], c.lo[k], c.hi[k] = cells[k], 0.0, float(max(cells[k], 1))
+    for k, v in enumerate((1.0, 2.0, 1.0)):
+        c.params[k] = v
+    h = ctypes.c_void_p()
+    rc = aderdg.lib().aderdg_create(ctypes.byref(c), None, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    msg = aderdg.lib().aderdg_last_error(None).decode()
+    assert ("2^31" in msg) if cells[1] else ("positive" in msg)
