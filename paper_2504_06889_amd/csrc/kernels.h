@@ -623,6 +623,13 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         for (int v = 0; v < V; v++) Qn[v] = active ? a.Q[(cell * V + v) * S + s] : 1.0;
     }
 
+    // volume term of the node (sum over directions of Kxi along fbar_j)
+    const int vp = a.vol_prec;
+    double vol[V];
+#pragma unroll
+    for (int v = 0; v < V; v++) vol[v] = 0.0;
+    bool vol_done = false;  // formed on the matrix cores with the predictor's buffers
+
     const bool src_here = active && cell == a.src_cell;
     const double src_phi = src_here ? a.src_phi[s] : 0.0;
     const int iters = a.iters;
@@ -784,22 +791,19 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
             oo[j] = PL::G::out_off(po[j], k);
         }
         __syncthreads();
-        // one slice: flux of q_b at every node, the derivative lines and the
-        // divergence at the node, whose FP64 value for variable v goes to
-        // sink(v, r) (descending v)
-        auto slice = [&](int b, auto &&sink) __attribute__((always_inline)) {
-            // the flux sees the FP32 rounding of the FP64 iterate
-            float qb[V];
-#pragma unroll
-            for (int v = 0; v < V; v++) qb[v] = (float)z[b][v];  // exact when FR
+        // One contraction pass on the matrix cores: the owners write the flux
+        // components flux_j(j, Fv, eta) of every direction (rounded to the
+        // format), M is applied along every line, and the owners sum their
+        // node's results over the directions in FP32: sink(rf, eta) with rf[v]
+        // the sum for variable v and eta[j] the derivative of the
+        // non-conservative input along j.
+        auto pass = [&](const MfmaPairs<PP, n> &M, auto &&flux_j, auto &&sink) __attribute__((always_inline)) {
             if (slot) {
 #pragma unroll
                 for (int j = 0; j < DIM; j++) {
-                    float Fv[V];
-                    Pde::flux(coef, qb, j, Fv);
-                    auto comp_val = [&](int c) -> float {
-                        return c < 0 ? 0.0f : (c == V ? ncp_value<Pde>(qb) : Fv[c < V ? c : 0]);
-                    };
+                    float Fv[V], ev;
+                    flux_j(j, Fv, ev);
+                    auto comp_val = [&](int c) -> float { return c < 0 ? 0.0f : (c == V ? ev : Fv[c < V ? c : 0]); };
 #pragma unroll
                     for (int p = 0; p < PL::NP; p++) {
                         T *dst = Fb + io[j] + p * PL::PSTRIDE;
@@ -810,11 +814,9 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 }
             }
             __syncthreads();
-            mp.template run<PL::NTILE, NWAVE, F>(Fb, Rb, wave, lane);
+            M.template run<PL::NTILE, NWAVE, F>(Fb, Rb, wave, lane);
             __syncthreads();
             if (active) {
-                // the divergence sum over directions is part of the FP32
-                // contraction
                 float rf[V], eta[DIM];
 #pragma unroll
                 for (int v = 0; v < V; v++) rf[v] = 0.0f;
@@ -834,15 +836,33 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                         }
                     }
                 }
-#pragma unroll
-                for (int v = V - 1; v >= 0; v--) {
-                    double rr = (double)rf[v];
-                    if constexpr (Pde::kNCP) {
-                        if (v >= 1 && v <= DIM) rr += (double)((float)coef.g * qb[0] * eta[v - 1]);
-                    }
-                    sink(v, rr);
-                }
+                sink(rf, eta);
             }
+        };
+        // One slice: flux of q_b at every node, the derivative lines and the
+        // divergence at the node, whose FP64 value for variable v goes to
+        // sink(v, r) (descending v).  The flux sees the FP32 rounding of the
+        // FP64 iterate (exact when FR).
+        auto slice = [&](int b, auto &&sink) __attribute__((always_inline)) {
+            float qb[V];
+#pragma unroll
+            for (int v = 0; v < V; v++) qb[v] = (float)z[b][v];
+            pass(
+                mp,
+                [&](int j, float *Fv, float &ev) __attribute__((always_inline)) {
+                    Pde::flux(coef, qb, j, Fv);
+                    ev = ncp_value<Pde>(qb);
+                },
+                [&](const float *rf, const float *eta) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int v = V - 1; v >= 0; v--) {
+                        double rr = (double)rf[v];
+                        if constexpr (Pde::kNCP) {
+                            if (v >= 1 && v <= DIM) rr += (double)((float)coef.g * qb[0] * eta[v - 1]);
+                        }
+                        sink(v, rr);
+                    }
+                });
         };
         // The first and the last iteration are peeled off the loop, so that
         // qbar, formed with the last iterate, is not carried through it.
@@ -857,6 +877,31 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 if (it < iters - 1 && active) update(false);
             }
             if (active) update(true);
+        }
+        // Volume integral on the matrix cores when its format is the
+        // predictor's 16-bit format (linear flux: fbar_j = F_j(qbar), FP64,
+        // rounded to the format; Kxi in the format; FP32 accumulation, the sum
+        // over the directions included).  In FP32 the four 16x16x4 steps per
+        // tile and the doubled LDS traffic cost more than the vector ALU path.
+        if constexpr (FR && PP != P32) {
+            if (vp == PP) {
+                MfmaPairs<PP, n> mk;
+                mk.init(B->Kxip[PP], lane);
+                pass(
+                    mk,
+                    [&](int j, float *Fv, float &ev) __attribute__((always_inline)) {
+                        double Fd[V];
+                        flux_dir<Pde, DIM>(coef, qbar, j, Fd);
+#pragma unroll
+                        for (int v = 0; v < V; v++) Fv[v] = (float)Fd[v];
+                        ev = 0.0f;
+                    },
+                    [&](const float *rf, const float *) __attribute__((always_inline)) {
+#pragma unroll
+                        for (int v = 0; v < V; v++) vol[v] = (double)rf[v];
+                    });
+                vol_done = true;
+            }
         }
     }
     __syncthreads();
@@ -899,20 +944,18 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     // ---------------- face projection and volume integral ----------------
     // Per direction j: the owners write qbar and fbar_j at their position on
     // the lines along j; one thread per (cell, var, face node) projects both
-    // lines onto the two faces (Alg. 1 "expansion") and applies Kxi along the
-    // fbar_j line (FP64, or inputs rounded to the volume format with FP32
-    // accumulation: one contraction per direction, so the vector ALU serves).
+    // lines onto the two faces (Alg. 1 "expansion") and, unless the matrix
+    // cores already formed the volume term, applies Kxi along the fbar_j line
+    // (FP64, or inputs rounded to the volume format with FP32 accumulation).
     // The owners then gather their node's volume term.  Two barriers per
     // direction: the line pass reads Ein and writes Evol, which the owners
     // only read after the second barrier and only overwrite (Ein) after it.
+    // The fbar_j lines are skipped when neither the faces (q-only faces) nor
+    // the volume term need them.
     using EL = EpiLayout<Pde, DIM, N>;
     double *Ein = reinterpret_cast<double *>(smem);                  // [n][NLPE]
     double *Evol = reinterpret_cast<double *>(smem + EL::in_bytes);  // [n][NLPV]
-    const int vp = a.vol_prec;
-    double vol[V];
-#pragma unroll
-    for (int v = 0; v < V; v++) vol[v] = 0.0;
-
+    const bool need_f = !vol_done || !(Pde::kLinear && a.flux_prec == P64);
 #pragma unroll 1
     for (int j = 0; j < DIM; j++) {
         // fbar_j = sum_a w_a F_j(q_a); for a linear flux this is F_j(qbar)
@@ -937,7 +980,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
 #pragma unroll
             for (int v = 0; v < V; v++) {
                 Ein[ij * EL::NLPE + ((cb * 2 + 0) * V + v) * F + fj] = active ? qbar[v] : 0.0;
-                Ein[ij * EL::NLPE + ((cb * 2 + 1) * V + v) * F + fj] = active ? fbj[v] : 0.0;
+                if (need_f) Ein[ij * EL::NLPE + ((cb * 2 + 1) * V + v) * F + fj] = active ? fbj[v] : 0.0;
             }
         }
         __syncthreads();
@@ -950,7 +993,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
 #pragma unroll
                 for (int k = 0; k < n; k++) {
                     xq[k] = Ein[k * EL::NLPE + ((cbi * 2 + 0) * V + v) * F + f];
-                    xf[k] = Ein[k * EL::NLPE + ((cbi * 2 + 1) * V + v) * F + f];
+                    xf[k] = need_f ? Ein[k * EL::NLPE + ((cbi * 2 + 1) * V + v) * F + f] : 0.0;
                 }
                 if (c < a.ncell) {
                     const long base = ((c * DIM + j) * 2) * 2 * V;
@@ -962,6 +1005,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                                                  side);
                     }
                 }
+                if (vol_done) continue;
                 if (vp == P64) {
 #pragma unroll
                     for (int i = 0; i < n; i++) {
@@ -994,7 +1038,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         default: line_pass(PrecC<PF16>{}); break;
         }
         __syncthreads();
-        if (active) {
+        if (active && !vol_done) {
             const int l0 = (cb * V) * F + fj;
 #pragma unroll
             for (int v = 0; v < V; v++) vol[v] += Evol[ij * EL::NLPV + l0 + v * F];
