@@ -278,6 +278,64 @@ def sweep():
     return out
 
 
+PAPER_RUNS = [("fp64", ("fp64",) * 3), ("predictor+volume=fp32", ("fp32", "fp32", "fp64")),
+              ("flux=fp32", ("fp64", "fp64", "fp32")), ("predictor+volume=bf16", ("bf16", "bf16", "fp64")),
+              ("predictor+volume=fp16", ("fp16", "fp16", "fp64")), ("all=fp32", ("fp32",) * 3),
+              ("all=bf16", ("bf16",) * 3), ("all=fp16", ("fp16",) * 3)]
+
+
+def paper_suite():
+    """The paper's 2-D scenarios of its mixed-precision study (27^2 cells, order 5, run to
+    t_end) with the state in FP64 and the predictor and volume contractions, the face
+    kernels, or all of them in a lower format (the paper's one-kernel-at-a-time design):
+    the L2 error of eq. L2gauss against the interpolant of the exact solution at t_end,
+    absolute (as the paper reports it) and relative, the relative L2 difference to the
+    FP64 GPU run and, for the lake at rest, the largest spurious momentum."""
+    import torch
+    from paper_2504_06889_amd import inputs
+    from paper_2504_06889_amd.aderdg import NonFiniteError, Solver
+    out = {}
+    for name, sc in inputs.PAPER_SUITE.items():
+        g = Solver.from_scenario(sc)
+        X = g.node_coords()
+        Q0 = torch.from_numpy(sc.initial_state(X)).cuda()
+        g.set_state(Q0)
+        t_end = sc.extra["t_end"]
+        nsteps = int(math.ceil(t_end / g.max_dt(sc.cfl)))
+        dt = t_end / nsteps
+        W = torch.from_numpy(g.weights()).cuda()
+        exact = torch.from_numpy(sc.initial_state(X, t_end)).cuda()
+        nex = l2(W, g.h, g.d, exact)
+        ref, runs = None, {}
+        for label, prec in PAPER_RUNS:
+            g.set_precisions(*prec)
+            g.set_state(Q0)
+            g.time = 0.0
+            r = {"precisions": dict(zip(("predictor", "volume", "flux"), prec))}
+            try:
+                g.step(dt, nsteps)
+                st = g.get_state(out=torch.empty(g.shape, dtype=torch.float64, device="cuda"))
+            except NonFiniteError as e:
+                r["error"] = "non-finite state: %s" % e
+                runs[label] = r
+                print("%s %s: non-finite" % (name, label), file=sys.stderr, flush=True)
+                continue
+            if ref is None:
+                ref = st
+            r["l2_vs_exact"] = l2(W, g.h, g.d, st, exact)
+            r["l2_rel_vs_exact"] = r["l2_vs_exact"] / nex
+            r["l2_rel_vs_fp64_gpu"] = l2(W, g.h, g.d, st, ref) / l2(W, g.h, g.d, ref)
+            if sc.pde == "swe":
+                r["max_abs_momentum"] = float(st[:, 1:3].abs().max())
+            runs[label] = r
+            print("%s %s: %s" % (name, label, ", ".join("%s %.3g" % (k, v) for k, v in r.items()
+                                                       if isinstance(v, float))), file=sys.stderr, flush=True)
+        out[name] = {"cells": list(sc.cells), "order": sc.order, "t_end": t_end, "steps": nsteps, "dt": dt,
+                     "runs": runs}
+        g.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -291,6 +349,8 @@ def main():
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--sweep", action="store_true",
                     help="only run the per-kernel precision sweep on the Euler and shallow-water workloads")
+    ap.add_argument("--paper-suite", action="store_true",
+                    help="only run the paper's 2-D scenarios (27^2 cells, order 5) with lower-format kernels")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (3 times), to scale HBM counters")
     args = ap.parse_args()
@@ -314,8 +374,8 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
         return
     torch.cuda.set_device(0)
-    if args.sweep:
-        txt = json.dumps({"sweep": sweep()})
+    if args.sweep or args.paper_suite:
+        txt = json.dumps({"sweep": sweep()} if args.sweep else {"paper_suite": paper_suite()})
         print(txt, flush=True)
         if args.out:
             with open(args.out, "w") as f:

@@ -242,6 +242,37 @@ SCENARIOS = {
          "checkpoint": 20, "c_mean": 1.5, "c_sigma": 0.2, "seed_c": 0, "seed_rec": 1}),
 }
 
+# The paper's 2-D scenarios of its mixed-precision study (Sec. 4, Sec. 5.4): 27^2 cells,
+# order 5, periodic.  Each runs to extra["t_end"] (steps = 0: the step count follows from
+# dt = C h / (d (2N+1) lambda_max) of the initial state); extra["exact"] says whether the
+# scenario has a closed-form solution at t_end.
+#  - acoustic planar wave (Sec. 4.2.1): [-1,1]^2, K = 4, rho = 1 (c = 2), wave along the
+#    diagonal, k = (pi, pi): the state returns to the initial one at t = sqrt(2) (t_end);
+#  - elastic planar waves (Sec. 4.2.1): [-1,1]^2, lambda = 2, mu = 1, rho = 1 (cp = 2,
+#    cs = 1), P wave along x (k = pi) and S wave along y (k = 2 pi), both of period 1 (t_end);
+#  - Euler Gaussian bell (Sec. 4.3.1): rho = 0.02 (1 + exp(-50 r^2)), v = (1, 1), p = 1 on
+#    [-1,1]^2, t_end = 2 (one period of the advection);
+#  - static isentropic vortex (Sec. 4.3.2): beta = 5 on [-5,5]^2, t_end = 10;
+#  - lake at rest (Sec. 4.4.1): b = sin(2 pi (x + y)), h = eta0 - b, eta0 = 2, g = 9.81 on
+#    [-1,1]^2, t_end = 1.
+PAPER_SUITE = {
+    "acoustic2d_n5_27_planar": Scenario(
+        "acoustic2d_n5_27_planar", "acoustic", 2, 5, (27, 27), (-1.0, -1.0), (1.0, 1.0), (1.0, 4.0), 0, 0.5,
+        "planar_acoustic", {"k": (math.pi, math.pi), "t_end": math.sqrt(2.0), "exact": True}),
+    "elastic2d_n5_27_planar": Scenario(
+        "elastic2d_n5_27_planar", "elastic", 2, 5, (27, 27), (-1.0, -1.0), (1.0, 1.0), (1.0, 2.0, 1.0), 0, 0.5,
+        "planar_elastic", {"kP": math.pi, "kS": 2 * math.pi, "t_end": 1.0, "exact": True}),
+    "euler2d_n5_27_bell": Scenario(
+        "euler2d_n5_27_bell", "euler", 2, 5, (27, 27), (-1.0, -1.0), (1.0, 1.0), (1.4,), 0, 0.5,
+        "euler_bell", {"t_end": 2.0, "exact": True}),
+    "euler2d_n5_27_vortex": Scenario(
+        "euler2d_n5_27_vortex", "euler", 2, 5, (27, 27), (-5.0, -5.0), (5.0, 5.0), (1.4,), 0, 0.5,
+        "euler_vortex", {"t_end": 10.0, "exact": True}),
+    "swe2d_n5_27_lake": Scenario(
+        "swe2d_n5_27_lake", "swe", 2, 5, (27, 27), (-1.0, -1.0), (1.0, 1.0), (9.81,), 0, 0.5,
+        "swe_lake", {"eta0": 2.0, "t_end": 1.0, "exact": True}),
+}
+
 
 def evaluate(sc, coords, t=0.0):
     """Initial (t = 0) or exact state of scenario `sc` at the given node coordinates."""
