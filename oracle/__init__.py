@@ -43,7 +43,9 @@ class _Config(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("order", ctypes.c_int), ("cells", ctypes.c_int * 3),
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3), ("pde", ctypes.c_int),
                 ("params", ctypes.c_double * 8), ("picard_iters", ctypes.c_int),
-                ("prec", ctypes.c_int * 3)]
+                ("prec", ctypes.c_int * 3), ("predictor", ctypes.c_int)]
+
+PREDICTORS = {"picard": 0, "ck": 1}
 
 
 _lib = None
@@ -125,7 +127,7 @@ class Oracle:
     """FP64 CPU ADER-DG on a periodic Cartesian grid (state layout [cell][var][node])."""
 
     def __init__(self, dim, order, cells, lo, hi, pde, params, picard_iters=0,
-                 prec=(FP64, FP64, FP64)):
+                 prec=(FP64, FP64, FP64), predictor="picard"):
         c = _Config()
         c.dim, c.order = dim, order
         cells = list(cells) + [1] * (3 - len(cells))
@@ -140,6 +142,8 @@ class Oracle:
         c.picard_iters = picard_iters
         for i in range(3):
             c.prec[i] = PREC_IDS.get(prec[i], prec[i])
+        c.predictor = PREDICTORS[predictor]
+        self.predictor = predictor
         self._cfg = c
         self._h = lib().or_create(ctypes.byref(c))
         if not self._h:

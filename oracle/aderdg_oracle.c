@@ -398,6 +398,9 @@ or_solver *or_create(const or_config *cfg)
     if (cfg->dim < 1 || cfg->dim > 3 || cfg->order < 0 || cfg->order + 1 > MAXN) return NULL;
     int V = or_nvars(cfg->pde, cfg->dim);
     if (V <= 0 || V > MAXV) return NULL;
+    if (cfg->predictor != OR_PICARD &&
+        (cfg->predictor != OR_CK || (cfg->pde != OR_ACOUSTIC && cfg->pde != OR_ELASTIC)))
+        return NULL; /* the CK procedure needs a linear flux */
     or_solver *s = (or_solver *)calloc(1, sizeof(or_solver));
     s->c = *cfg;
     s->d = cfg->dim;
@@ -451,7 +454,7 @@ int or_set_material(or_solver *s, const double *c_per_cell)
  * s(t) phi_k(xs) / (h^d W_k) (W_k = product of Gauss weights).             */
 int or_set_source(or_solver *s, const double *x, double f0, double t0, double amp)
 {
-    if (s->c.pde != OR_ACOUSTIC) return -1;
+    if (s->c.pde != OR_ACOUSTIC || s->c.predictor != OR_PICARD) return -1;
     int64_t cell = 0, m = 1;
     double loc[3];
     for (int i = 0; i < s->d; i++) {
@@ -595,11 +598,59 @@ static void slice_residual(const or_solver *s, int64_t cell, const double *qb, d
  *   qbar [V][S]     time average sum_a w_a q_a                 (FP64)
  *   fbar [d][V][S]  time averages sum_a w_a F_j(q_a)           (FP64)
  *   nbar [V][S]     time average of sum_j B_j(q_a) D_j q_a     (FP64; SWE) */
+/* Cauchy-Kowalevskaya predictor of one cell (linear flux, no source): with
+ * dq/dt = -R(q) (R the spatial divergence of slice_residual), the Taylor terms
+ * T_k = dt^k/k! d^kq/dt^k follow from T_0 = Q, T_k = -(dt/k) R(T_{k-1}),
+ * k = 1..N.  The cell-local solution is q(t + tau dt) = sum_k T_k tau^k, its
+ * time average over the step sum_k T_k / (k+1), and (linear flux) the flux
+ * average F_j of that average.  Outputs as for predict(); qst holds the
+ * expansion at the n time nodes. */
+static void predict_ck(const or_solver *s, int64_t cell, const double *Q, double t, double dt,
+                       cell_work *w, double *qst, double *qbar, double *fbar, double *nbar)
+{
+    const int n = s->n, S = s->S, V = s->V, d = s->d;
+    const size_t VS = (size_t)V * S;
+    double *T = w->q;                /* all n Taylor terms, [k][V][S] */
+    memcpy(T, Q, VS * sizeof(double));
+    for (int k = 1; k < n; k++) {
+        slice_residual(s, cell, T + (k - 1) * VS, t, w, w->R);
+        for (size_t i = 0; i < VS; i++) T[k * VS + i] = -(dt / k) * w->R[i];
+    }
+    double *avg = w->qn;
+    for (size_t i = 0; i < VS; i++) {
+        double acc = 0.0;
+        for (int k = 0; k < n; k++) acc += T[k * VS + i] / (k + 1);
+        avg[i] = acc;
+    }
+    if (qst)
+        for (int a = 0; a < n; a++)
+            for (size_t i = 0; i < VS; i++) {
+                double acc = 0.0, tp = 1.0;
+                for (int k = 0; k < n; k++) { acc += T[k * VS + i] * tp; tp *= s->xi[a]; }
+                qst[a * VS + i] = acc;
+            }
+    if (qbar) memcpy(qbar, avg, VS * sizeof(double));
+    if (fbar)
+        for (int sn = 0; sn < S; sn++) {
+            double q[MAXV], F[MAXV];
+            for (int v = 0; v < V; v++) q[v] = avg[v * S + sn];
+            for (int j = 0; j < d; j++) {
+                pde_flux(s, cell, q, j, F);
+                for (int v = 0; v < V; v++) fbar[(j * V + v) * S + sn] = F[v];
+            }
+        }
+    if (nbar) memset(nbar, 0, sizeof(double) * VS);
+}
+
 static void predict(const or_solver *s, int64_t cell, const double *Q, double t, double dt,
                     cell_work *w, double *qst, double *qbar, double *fbar, double *nbar)
 {
     const int n = s->n, S = s->S, V = s->V, d = s->d;
     const size_t VS = (size_t)V * S;
+    if (s->c.predictor == OR_CK) {
+        predict_ck(s, cell, Q, t, dt, w, qst, qbar, fbar, nbar);
+        return;
+    }
     for (int a = 0; a < n; a++) memcpy(w->q + a * VS, Q, VS * sizeof(double));
     for (int r = 0; r < s->I; r++) {
         for (int b = 0; b < n; b++)
@@ -939,7 +990,7 @@ static void acoustic_flux_transpose(int d, double K, double rho, const double *x
 int or_adjoint_step(or_solver *s, const double *Qn, double t, double dt, const double *lam,
                     double *mu, double *grad)
 {
-    if (s->c.pde != OR_ACOUSTIC || !s->cmat) return -1;
+    if (s->c.pde != OR_ACOUSTIC || !s->cmat || s->c.predictor != OR_PICARD) return -1;
     if (s->c.prec[0] || s->c.prec[1] || s->c.prec[2]) return -1;
     const int n = s->n, S = s->S, V = s->V, d = s->d, F = s->F, I = s->I;
     const size_t VS = (size_t)V * S, FS = (size_t)d * 2 * V * F;

@@ -24,7 +24,12 @@
  *     hv, 0) and the face fluctuation 0.5 g hbar (eta+ - eta-) enters the
  *     normal momentum (left cell: G + Dq, right cell: G - Dq);
  *   - point source (acoustics only): s(t) delta(x - xs) in the pressure
- *     equation, s a Ricker wavelet, included in predictor and corrector.
+ *     equation, s a Ricker wavelet, included in predictor and corrector;
+ *   - Cauchy-Kowalevskaya predictor (linear PDEs, the paper's alternative to
+ *     the Picard iteration, Sec. 2): the Taylor expansion of the cell-local
+ *     solution in time to degree N, its time derivatives taken from the PDE
+ *     (d/dt = minus the discrete divergence, applied repeatedly); the time
+ *     average of the truncated expansion replaces the Picard time average.
  *
  * Emulated precision (prec[0] predictor, prec[1] volume, prec[2] flux; values
  * OR_FP64/OR_FP32/OR_BF16/OR_FP16): the inputs of the contraction (data and
@@ -45,6 +50,7 @@
 
 enum { OR_ACOUSTIC = 0, OR_ELASTIC = 1, OR_EULER = 2, OR_SWE = 3 };
 enum { OR_FP64 = 0, OR_FP32 = 1, OR_BF16 = 2, OR_FP16 = 3 };
+enum { OR_PICARD = 0, OR_CK = 1 };
 
 typedef struct {
     int dim, order;
@@ -54,6 +60,7 @@ typedef struct {
     double params[8]; /* acoustic: rho, K | elastic: rho, lambda, mu | euler: gamma | swe: g */
     int picard_iters; /* 0 -> order + 1 */
     int prec[3];      /* emulated precision: predictor, volume, flux */
+    int predictor;    /* OR_PICARD, or OR_CK (linear PDEs without a point source) */
 } or_config;
 
 typedef struct or_solver {
