@@ -343,6 +343,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="elastic3d_n5_64")
     ap.add_argument("--variants", default="fp64,fp32,bf16,fp16")
+    ap.add_argument("--ck-variants", default="fp64,fp16",
+                    help="precisions run with the Cauchy-Kowalevskaya predictor (linear PDEs), reported beside")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -399,8 +401,12 @@ def main():
 
     runs = {}
     states = {}
-    for p in args.variants.split(","):
+    labels = [(p, "picard", p) for p in args.variants.split(",") if p]
+    if sc.pde in ("acoustic", "elastic"):
+        labels += [("ck_" + p, "ck", p) for p in args.ck_variants.split(",") if p]
+    for label, kind, p in labels:
         prec = ("fp64", "fp64", "fp64") if p == "fp64" else (p, p, "fp64")
+        g.set_predictor(kind)
         g.set_precisions(*prec)
         g.set_state(Q0)
         g.time = 0.0
@@ -416,8 +422,9 @@ def main():
         g.set_timing(False)
         out = torch.empty(g.shape, dtype=torch.float64, device="cuda")
         g.get_state(out)
+        p = label
         states[p] = out
-        runs[p] = {"precisions": {"predictor": prec[0], "volume": prec[1], "flux": prec[2]},
+        runs[p] = {"predictor": kind, "precisions": {"predictor": prec[0], "volume": prec[1], "flux": prec[2]},
                    "ms_per_step": 1e3 * el / args.steps, "dof_per_s": dof * args.steps / el,
                    "kernel_ms_per_step": (tm["predictor_ms"] + tm["corrector_ms"] + tm["fused_ms"]) / max(tm["steps"], 1),
                    "fused_kernel_ms": tm["fused_ms"] / max(tm["fused_launches"], 1),
@@ -425,13 +432,21 @@ def main():
         print("%s: %.3f ms/step (kernels %.3f ms/step, fused corrector+predictor kernel %.3f ms)" % (
             p, runs[p]["ms_per_step"], runs[p]["kernel_ms_per_step"], runs[p]["fused_kernel_ms"]), file=sys.stderr,
             flush=True)
-    if "fp64" in states:
-        nref = l2(W, g.h, g.d, states["fp64"])
+    # each predictor's lower-format runs against its own FP64 run; speed-ups against
+    # the FP64 Picard path
+    for kind, ref in (("picard", "fp64"), ("ck", "ck_fp64")):
+        if ref not in states:
+            continue
+        nref = l2(W, g.h, g.d, states[ref])
         for p in runs:
-            runs[p]["l2_rel_vs_fp64_gpu"] = l2(W, g.h, g.d, states[p], states["fp64"]) / nref
-            runs[p]["tolerance"] = TOL[p]
-            runs[p]["within_tolerance"] = bool(runs[p]["l2_rel_vs_fp64_gpu"] <= TOL[p])
-            runs[p]["speedup_vs_fp64"] = runs["fp64"]["ms_per_step"] / runs[p]["ms_per_step"]
+            if runs[p]["predictor"] != kind:
+                continue
+            fmt = runs[p]["precisions"]["predictor"]
+            runs[p]["l2_rel_vs_fp64_gpu"] = l2(W, g.h, g.d, states[p], states[ref]) / nref
+            runs[p]["tolerance"] = TOL[fmt]
+            runs[p]["within_tolerance"] = bool(runs[p]["l2_rel_vs_fp64_gpu"] <= TOL[fmt])
+            if "fp64" in runs:
+                runs[p]["speedup_vs_fp64"] = runs["fp64"]["ms_per_step"] / runs[p]["ms_per_step"]
 
     # roofline of the dominant kernel (the fused corrector + predictor) for each variant
     traffic = measured_traffic() if args.workload == "elastic3d_n5_64" else {}
@@ -439,6 +454,8 @@ def main():
     mf, v64, fl = predictor_flops(sc.pde, sc.dim, sc.order, g.V, I)
     v64 += corrector_flops(sc.dim, sc.order, g.V)
     for p in runs:
+        if runs[p]["predictor"] != "picard":
+            continue  # the roofline counts are the Picard predictor's
         t = runs[p]["fused_kernel_ms"] * 1e-3
         total = (mf + v64 + fl) * g.ncell
         if p == "fp64":
@@ -459,7 +476,7 @@ def main():
     g.close()
     del states, Q0, exact
     torch.cuda.empty_cache()
-    head = HEADLINE if HEADLINE in runs else list(runs)[-1]
+    head = HEADLINE if HEADLINE in runs else [p for p in runs if runs[p]["predictor"] == "picard"][-1]
     r = runs[head]
     line = {
         "metric": "cell-DOF updates/s, mixed vs FP64 GPU at stated L2 error; adjoint/forward time",

@@ -61,6 +61,12 @@ typedef enum { ADERDG_ACOUSTIC = 0, ADERDG_ELASTIC = 1, ADERDG_EULER = 2, ADERDG
 typedef enum { ADERDG_K_PREDICTOR = 0, ADERDG_K_VOLUME = 1, ADERDG_K_FLUX = 2, ADERDG_K_STORAGE = 3 } aderdg_kernel;
 typedef enum { ADERDG_FP64 = 0, ADERDG_FP32 = 1, ADERDG_BF16 = 2, ADERDG_FP16 = 3 } aderdg_prec;
 
+/* Space-time predictor (Sec. 2): the Picard iteration of eq. Picard, or, for
+ * linear PDEs, the Cauchy-Kowalevskaya procedure the paper names as the
+ * cheaper alternative (time derivatives from the PDE, Taylor expansion to
+ * degree N in time).                                                         */
+typedef enum { ADERDG_PICARD = 0, ADERDG_CK = 1 } aderdg_predictor;
+
 typedef struct {
     int dim;          /* 2 or 3 (shallow water: 2)                                    */
     int order;        /* polynomial order N (n = N+1 nodes per dimension)             */
@@ -96,6 +102,15 @@ aderdg_status aderdg_get_state(aderdg_solver *s, double *Q, int is_device);
 /* Per-cell sound speed c (acoustics only; K = rho c^2 per cell, Rusanov speed
  * max(c_L, c_R) at each face).  `c` holds one double per cell.               */
 aderdg_status aderdg_set_material(aderdg_solver *s, const double *c, int is_device);
+
+/* Select the space-time predictor (aderdg_predictor; default PICARD).  CK: the
+ * Taylor terms T_0 = Q, T_k = -(dt/k) R(T_{k-1}) (R the divergence of the
+ * cell-local fluxes, its contraction in the PREDICTOR precision) for
+ * k = 1..N, time average sum_k T_k/(k+1) in FP64; face data and volume term
+ * from that average as for Picard.  Errors: INVALID (unknown kind),
+ * UNSUPPORTED (CK for a nonlinear PDE, or with a point source set).  The
+ * adjoint and point sources need PICARD.                                      */
+aderdg_status aderdg_set_predictor(aderdg_solver *s, int kind);
 
 /* Select the precision of one kernel's contractions (see aderdg_kernel).
  * Errors: INVALID (unknown kernel/precision), UNSUPPORTED (STORAGE != FP64).  */

@@ -41,7 +41,9 @@ EXPORTS = [
     "aderdg_set_source", "aderdg_set_receivers", "aderdg_read_receivers", "aderdg_step_adjoint",
     "aderdg_receivers_adjoint", "aderdg_nodes", "aderdg_info", "aderdg_state_ptr", "aderdg_last_error",
     "aderdg_set_timing", "aderdg_get_timing", "aderdg_copy_faces", "aderdg_step_adjoint_faces",
+    "aderdg_set_predictor",
 ]
+PREDICTORS = {"picard": 0, "ck": 1}
 
 _lib = None
 
@@ -79,6 +81,7 @@ def lib():
         "aderdg_get_timing": [vp, dp],
         "aderdg_copy_faces": [vp, vp, i],
         "aderdg_step_adjoint_faces": [vp, d, d, vp, vp, vp, vp],
+        "aderdg_set_predictor": [vp, i],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -200,6 +203,11 @@ class Solver:
         k = KERNEL[kernel] if isinstance(kernel, str) else int(kernel)
         p = PREC[prec] if isinstance(prec, str) else int(prec)
         self._check(lib().aderdg_set_precision(self._h, k, p))
+
+    def set_predictor(self, kind):
+        """"picard" (eq. Picard) or "ck" (Cauchy-Kowalevskaya, linear PDEs)."""
+        self._check(lib().aderdg_set_predictor(self._h, PREDICTORS[kind] if isinstance(kind, str) else int(kind)))
+        self.predictor = kind
 
     def set_precisions(self, predictor="fp64", volume="fp64", flux="fp64"):
         self.set_precision("predictor", predictor)

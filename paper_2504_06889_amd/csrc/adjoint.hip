@@ -91,7 +91,7 @@ int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::stri
     // 2. forward face data of this step (unless the caller kept them)
     const void *fwd = a.fwdface ? a.fwdface : w.fwdface;
     if (!a.fwdface) {
-        StepArgs f;
+        StepArgs f{};  // zero: Picard predictor, no fused input
         f.Q = const_cast<double *>(a.Qn);
         f.faces = w.fwdface;
         f.B = a.B;

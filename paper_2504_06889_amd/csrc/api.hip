@@ -92,6 +92,7 @@ struct aderdg_solver {
     unsigned long long *dScalar = nullptr;
     int *dFlag = nullptr;
     int prec[4] = {0, 0, 0, 0};
+    int predictor = ADERDG_PICARD;
     AdjointWork adj;
     bool timing = false;
     std::vector<hipEvent_t> ev;  // 2 events per timed launch
@@ -289,6 +290,18 @@ aderdg_status aderdg_set_material(aderdg_solver *s, const double *c, int is_devi
     return ADERDG_OK;
 }
 
+aderdg_status aderdg_set_predictor(aderdg_solver *s, int kind) {
+    if (!s) return ADERDG_E_INVALID;
+    if (kind != ADERDG_PICARD && kind != ADERDG_CK) FAIL(s, ADERDG_E_INVALID, "unknown predictor %d", kind);
+    if (kind == ADERDG_CK) {
+        if (s->cfg.pde != ADERDG_ACOUSTIC && s->cfg.pde != ADERDG_ELASTIC)
+            FAIL(s, ADERDG_E_UNSUPPORTED, "the Cauchy-Kowalevskaya predictor needs a linear PDE");
+        if (s->src_cell >= 0) FAIL(s, ADERDG_E_UNSUPPORTED, "the Cauchy-Kowalevskaya predictor takes no point source");
+    }
+    s->predictor = kind;
+    return ADERDG_OK;
+}
+
 aderdg_status aderdg_set_precision(aderdg_solver *s, int kernel, int prec) {
     if (!s) return ADERDG_E_INVALID;
     if (kernel < 0 || kernel > 3 || prec < 0 || prec > 3) FAIL(s, ADERDG_E_INVALID, "unknown kernel or precision");
@@ -322,7 +335,7 @@ aderdg_status aderdg_max_dt(aderdg_solver *s, double cfl, double *dt_out) {
 }
 
 static StepArgs step_args(aderdg_solver *s, double dt, double t) {
-    StepArgs a;
+    StepArgs a{};
     a.Q = s->dQ;
     a.faces = s->dFaces;
     a.faces_in = nullptr;
@@ -338,6 +351,7 @@ static StepArgs step_args(aderdg_solver *s, double dt, double t) {
     a.vol_prec = s->prec[ADERDG_K_VOLUME];
     a.flux_prec = s->prec[ADERDG_K_FLUX];
     a.iters = s->iters;
+    a.ck = s->predictor == ADERDG_CK;
     a.write_state = 1;
     a.src_cell = s->src_cell;
     a.src_phi = s->dSrcPhi;
@@ -459,6 +473,8 @@ static bool locate(const aderdg_solver *s, const double *x, long *cell, double *
 aderdg_status aderdg_set_source(aderdg_solver *s, const double x[3], double f0, double t0, double amp) {
     if (!s || !x) return ADERDG_E_INVALID;
     if (s->cfg.pde != ADERDG_ACOUSTIC) FAIL(s, ADERDG_E_UNSUPPORTED, "point sources are for acoustics only");
+    if (s->predictor != ADERDG_PICARD)
+        FAIL(s, ADERDG_E_UNSUPPORTED, "point sources need the Picard predictor");
     long cell;
     double loc[3];
     if (!locate(s, x, &cell, loc)) FAIL(s, ADERDG_E_INVALID, "source outside the domain");
@@ -536,6 +552,7 @@ static aderdg_status step_adjoint(aderdg_solver *s, double dt, double t, const d
         FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint is built for acoustics with a per-cell material");
     if (s->prec[ADERDG_K_PREDICTOR] || s->prec[ADERDG_K_VOLUME] || s->prec[ADERDG_K_FLUX])
         FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint is FP64 only");
+    if (s->predictor != ADERDG_PICARD) FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint differentiates the Picard predictor");
     AdjointArgs a;
     a.pred = s->ks->pred[0];
     a.cfg_pde = s->cfg.pde;

@@ -36,6 +36,7 @@ struct StepArgs {
     int vol_prec, flux_prec;
     int iters;            // Picard iterations
     int write_state;      // 0: only the face data is produced (Q untouched)
+    int ck;               // 1: Cauchy-Kowalevskaya predictor (linear PDEs, no source)
     long src_cell;        // -1: no source
     const double *src_phi;
     double src_f0, src_t0, src_amp;
@@ -719,58 +720,90 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
             }
         }
     };
+    // Cauchy-Kowalevskaya procedure (linear flux, no source): the Taylor terms
+    // T_k = dt^k/k! d^kq/dt^k from T_0 = Qn, T_k = -(sigma/k) h R(T_{k-1}),
+    // k = 1..N, with h R the divergence of one slice; qbar = sum_k T_k/(k+1)
+    // (FP64).  The terms only feed the next slice's flux and qbar.
+    constexpr bool CKOK = Pde::kLinear && !Pde::kNCP;
+    const bool ck = CKOK && a.ck;
+    auto ck_run = [&](auto &&slice_fn) __attribute__((always_inline)) {
+        double Tk[V];
+#pragma unroll
+        for (int v = 0; v < V; v++) {
+            Tk[v] = Qn[v];
+            qbar[v] = Qn[v];
+        }
+#pragma unroll 1
+        for (int k = 1; k < n; k++) {
+            const double sk = -a.sigma / k, ik = 1.0 / (k + 1);
+            slice_fn(Tk, [&](int v, double r) __attribute__((always_inline)) {
+                Tk[v] = sk * r;
+                qbar[v] = fma(Tk[v], ik, qbar[v]);
+            });
+        }
+    };
     if constexpr (PP == P64) {
         double *X = reinterpret_cast<double *>(smem);  // [n][NLP] position-major
-#pragma unroll 1
-        for (int it = 0; it < iters; it++) {
+        // one slice: flux of the state qb at every node into the lines, the
+        // derivative along every line (in place), and the divergence at the
+        // node passed to sink(v, h R_v) in descending v
+        auto slice = [&](const double *qb, auto &&sink) __attribute__((always_inline)) {
+            if (slot) {
 #pragma unroll
-            for (int b = 0; b < n; b++) {
-                if (it == 0 && b > 0) continue;
-                if (slot) {
+                for (int j = 0; j < DIM; j++) {
+                    double Fv[V];
+                    Pde::flux(coef, qb, j, Fv);
 #pragma unroll
-                    for (int j = 0; j < DIM; j++) {
-                        double Fv[V];
-                        Pde::flux(coef, z[b], j, Fv);
-#pragma unroll
-                        for (int i = 0; i < PL::NZ; i++) {
-                            const int c = PL::FS::comp(j, i);
-                            X[po[j] + i * PL::VSTRIDE] = c == V ? ncp_value<Pde>(z[b]) : Fv[c < V ? c : 0];
-                        }
-                    }
-                }
-                __syncthreads();
-                for (int Ln = tid; Ln < PL::NL; Ln += TPB) {
-                    double x[n];
-#pragma unroll
-                    for (int k = 0; k < n; k++) x[k] = X[k * PL::NLP + Ln];
-#pragma unroll
-                    for (int i = 0; i < n; i++) {
-                        double y = 0.0;
-#pragma unroll
-                        for (int k = 0; k < n; k++) y = fma(B->D[i][k], x[k], y);
-                        X[i * PL::NLP + Ln] = y;
-                    }
-                }
-                __syncthreads();
-                if (active) {
-                    // descending v: the non-conservative term of v >= 1 reads q_b[0]
-#pragma unroll
-                    for (int v = V - 1; v >= 0; v--) {
-                        double r = 0.0;
-#pragma unroll
-                        for (int j = 0; j < DIM; j++) {
-                            const int i = PL::FS::index(j, v);
-                            if (i >= 0) r += X[po[j] + i * PL::VSTRIDE];
-                        }
-                        if constexpr (Pde::kNCP) {
-                            if (v >= 1 && v <= DIM)
-                                r += coef.g * z[b][0] * X[po[v - 1] + PL::FS::index(v - 1, V) * PL::VSTRIDE];
-                        }
-                        fold(it, b, v, r, iters == 1);
+                    for (int i = 0; i < PL::NZ; i++) {
+                        const int c = PL::FS::comp(j, i);
+                        X[po[j] + i * PL::VSTRIDE] = c == V ? ncp_value<Pde>(qb) : Fv[c < V ? c : 0];
                     }
                 }
             }
-            if (it > 0 && active) update(it == iters - 1);
+            __syncthreads();
+            for (int Ln = tid; Ln < PL::NL; Ln += TPB) {
+                double x[n];
+#pragma unroll
+                for (int k = 0; k < n; k++) x[k] = X[k * PL::NLP + Ln];
+#pragma unroll
+                for (int i = 0; i < n; i++) {
+                    double y = 0.0;
+#pragma unroll
+                    for (int k = 0; k < n; k++) y = fma(B->D[i][k], x[k], y);
+                    X[i * PL::NLP + Ln] = y;
+                }
+            }
+            __syncthreads();
+            if (active) {
+                // descending v: the non-conservative term of v >= 1 reads q_b[0]
+#pragma unroll
+                for (int v = V - 1; v >= 0; v--) {
+                    double r = 0.0;
+#pragma unroll
+                    for (int j = 0; j < DIM; j++) {
+                        const int i = PL::FS::index(j, v);
+                        if (i >= 0) r += X[po[j] + i * PL::VSTRIDE];
+                    }
+                    if constexpr (Pde::kNCP) {
+                        if (v >= 1 && v <= DIM)
+                            r += coef.g * qb[0] * X[po[v - 1] + PL::FS::index(v - 1, V) * PL::VSTRIDE];
+                    }
+                    sink(v, r);
+                }
+            }
+        };
+        if (ck) {
+            if constexpr (CKOK) ck_run(slice);
+        } else {
+#pragma unroll 1
+            for (int it = 0; it < iters; it++) {
+#pragma unroll
+                for (int b = 0; b < n; b++) {
+                    if (it == 0 && b > 0) continue;
+                    slice(z[b], [&](int v, double r) __attribute__((always_inline)) { fold(it, b, v, r, iters == 1); });
+                }
+                if (it > 0 && active) update(it == iters - 1);
+            }
         }
     } else {
         using T = typename Store<PP>::T;
@@ -866,7 +899,24 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         };
         // The first and the last iteration are peeled off the loop, so that
         // qbar, formed with the last iterate, is not carried through it.
-        if (iters == 1) {
+        if (ck) {
+            if constexpr (CKOK)
+                ck_run([&](const double *Tk, auto &&sink) __attribute__((always_inline)) {
+                    float qb[V];
+#pragma unroll
+                    for (int v = 0; v < V; v++) qb[v] = (float)Tk[v];
+                    pass(
+                        mp,
+                        [&](int j, float *Fv, float &ev) __attribute__((always_inline)) {
+                            Pde::flux(coef, qb, j, Fv);
+                            ev = 0.0f;
+                        },
+                        [&](const float *rf, const float *) __attribute__((always_inline)) {
+#pragma unroll
+                            for (int v = V - 1; v >= 0; v--) sink(v, (double)rf[v]);
+                        });
+                });
+        } else if (iters == 1) {
             slice(0, [&](int v, double r) __attribute__((always_inline)) { fold(0, 0, v, r, true); });
         } else {
             slice(0, [&](int v, double r) __attribute__((always_inline)) { fold(0, 0, v, r, false); });
@@ -913,8 +963,10 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     for (int v = 0; v < V; v++) {
         nbar[v] = 0.0;
         if constexpr (!FR) {
+            if (!ck) {
 #pragma unroll
-            for (int t = 0; t < n; t++) qbar[v] = fma(B->w[t], z[t][v], qbar[v]);
+                for (int t = 0; t < n; t++) qbar[v] = fma(B->w[t], z[t][v], qbar[v]);
+            }
         }
     }
     if constexpr (Pde::kNCP) {
