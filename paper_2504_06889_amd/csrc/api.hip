@@ -553,7 +553,7 @@ static aderdg_status step_adjoint(aderdg_solver *s, double dt, double t, const d
     if (s->prec[ADERDG_K_PREDICTOR] || s->prec[ADERDG_K_VOLUME] || s->prec[ADERDG_K_FLUX])
         FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint is FP64 only");
     if (s->predictor != ADERDG_PICARD) FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint differentiates the Picard predictor");
-    AdjointArgs a;
+    AdjointArgs a{};
     a.pred = s->ks->pred[0];
     a.cfg_pde = s->cfg.pde;
     a.dim = s->d;
