@@ -23,6 +23,7 @@ struct AdjointArgs {
     long src_cell;
     const double *src_phi;
     double src_f0, src_t0, src_amp;
+    double src_s[kMaxN], src_bar;  // the forward predictor's source values (StepArgs)
 };
 
 // Device work buffers owned by a solver for the adjoint.

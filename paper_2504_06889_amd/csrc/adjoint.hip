@@ -109,9 +109,8 @@ int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::stri
         f.write_state = 0;
         f.src_cell = a.src_cell;
         f.src_phi = a.src_phi;
-        f.src_f0 = a.src_f0;
-        f.src_t0 = a.src_t0;
-        f.src_amp = a.src_amp;
+        for (int b = 0; b < kMaxN; b++) f.src_s[b] = a.src_s[b];
+        f.src_bar = a.src_bar;
         a.pred(f, st);
     }
     // 3. the adjoint proper

@@ -334,6 +334,23 @@ aderdg_status aderdg_max_dt(aderdg_solver *s, double cfl, double *dt_out) {
     return ADERDG_OK;
 }
 
+// The point source's time function (Ricker wavelet) at the n time nodes of the
+// step [t, t + dt], times h, and its time average (zero without a source).
+static double ricker_host(double t, double f0, double t0, double amp) {
+    const double x = M_PI * f0 * (t - t0), q = x * x;
+    return amp * (1.0 - 2.0 * q) * std::exp(-q);
+}
+static void source_values(const aderdg_solver *s, double t, double dt, double *src_s, double *src_bar) {
+    *src_bar = 0.0;
+    for (int b = 0; b < kMaxN; b++) src_s[b] = 0.0;
+    if (s->src_cell < 0) return;
+    for (int b = 0; b < s->n; b++) {
+        const double r = ricker_host(t + s->hB.xi[b] * dt, s->src_f0, s->src_t0, s->src_amp);
+        src_s[b] = s->h * r;
+        *src_bar += s->hB.w[b] * r;
+    }
+}
+
 static StepArgs step_args(aderdg_solver *s, double dt, double t) {
     StepArgs a{};
     a.Q = s->dQ;
@@ -355,9 +372,7 @@ static StepArgs step_args(aderdg_solver *s, double dt, double t) {
     a.write_state = 1;
     a.src_cell = s->src_cell;
     a.src_phi = s->dSrcPhi;
-    a.src_f0 = s->src_f0;
-    a.src_t0 = s->src_t0;
-    a.src_amp = s->src_amp;
+    source_values(s, t, dt, a.src_s, &a.src_bar);
     return a;
 }
 
@@ -576,6 +591,7 @@ static aderdg_status step_adjoint(aderdg_solver *s, double dt, double t, const d
     a.src_f0 = s->src_f0;
     a.src_t0 = s->src_t0;
     a.src_amp = s->src_amp;
+    source_values(s, t, dt, a.src_s, &a.src_bar);
     std::string msg;
     const int rc = adjoint_step(s->adj, a, s->stream, msg);
     if (rc != 0) {

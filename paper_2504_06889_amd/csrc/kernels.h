@@ -39,7 +39,9 @@ struct StepArgs {
     int ck;               // 1: Cauchy-Kowalevskaya predictor (linear PDEs, no source)
     long src_cell;        // -1: no source
     const double *src_phi;
-    double src_f0, src_t0, src_amp;
+    // point source: h s(t + xi_b dt) at the n time nodes and the time average
+    // sum_b w_b s(t + xi_b dt) (uniform values, evaluated on the host)
+    double src_s[kMaxN], src_bar;
 };
 
 // Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
@@ -675,7 +677,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         else po[j] = ((cb * DIM + j) * PL::NP) * F + f;
     }
     auto src_term = [&](int b) {
-        return a.h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi;
+        return a.src_s[b] * src_phi;
     };
     // fold h R_b (variable v, slice b) into the iterate rows; `last`: the
     // first iteration is also the last one
@@ -1098,12 +1100,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     }
 
     if (active && a.write_state) {
-        double sbar = 0.0;
-        if (src_here) {
-#pragma unroll
-            for (int t = 0; t < n; t++)
-                sbar += B->w[t] * ricker(a.t + B->xi[t] * a.dt, a.src_f0, a.src_t0, a.src_amp);
-        }
+        const double sbar = a.src_bar;
 #pragma unroll
         for (int v = 0; v < V; v++) {
             double qn = Qn[v] + a.sigma * vol[v];
