@@ -1010,8 +1010,36 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     double *Ein = reinterpret_cast<double *>(smem);                  // [n][NLPE]
     double *Evol = reinterpret_cast<double *>(smem + EL::in_bytes);  // [n][NLPV]
     const bool need_f = !vol_done || !(Pde::kLinear && a.flux_prec == P64);
+    if (!need_f) {
+        // Only the FP64 faces of qbar are left: one node-major copy of qbar
+        // serves the lines of every direction, one pass and one barrier.
+        double *Qb = reinterpret_cast<double *>(smem);  // [CPB][V][S]
+        if (slot) {
+#pragma unroll
+            for (int v = 0; v < V; v++) Qb[(cb * V + v) * S + s] = active ? qbar[v] : 0.0;
+        }
+        __syncthreads();
+        for (int L = tid; L < CPB * DIM * V * F; L += TPB) {
+            const int f = L % F;
+            int r = L / F;
+            const int v = r % V;
+            r /= V;
+            const int j = r % DIM, cbi = r / DIM;
+            const long c = cell0 + cbi;
+            if (c >= a.ncell) continue;
+            const int st = j == 0 ? 1 : (j == 1 ? n : n * n);
+            const double *line = Qb + (cbi * V + v) * S + line_start<n>(f, j);
+            double xq[n];
+#pragma unroll
+            for (int k = 0; k < n; k++) xq[k] = line[k * st];
+            const long base = ((c * DIM + j) * 2) * 2 * V;
+#pragma unroll
+            for (int side = 0; side < 2; side++)
+                project_store<P64, n>(a.faces, ((base + (side * 2 + 0) * V) + v) * (long)F + f, xq, B, side);
+        }
+    }
 #pragma unroll 1
-    for (int j = 0; j < DIM; j++) {
+    for (int j = 0; j < (need_f ? DIM : 0); j++) {
         // fbar_j = sum_a w_a F_j(q_a); for a linear flux this is F_j(qbar)
         double fbj[V];
         if constexpr (Pde::kLinear) {
