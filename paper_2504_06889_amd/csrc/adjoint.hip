@@ -131,9 +131,7 @@ int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::stri
     k.iters = a.iters;
     k.src_cell = a.src_cell;
     k.src_phi = a.src_phi;
-    k.src_f0 = a.src_f0;
-    k.src_t0 = a.src_t0;
-    k.src_amp = a.src_amp;
+    for (int b = 0; b < kMaxN; b++) k.src_s[b] = a.src_s[b];
     it->second.second(k, st);
     if (hipGetLastError() != hipSuccess) {
         msg = "adjoint kernel launch failed";

@@ -35,7 +35,7 @@ struct AdjKArgs {
     int iters;
     long src_cell;
     const double *src_phi;
-    double src_f0, src_t0, src_amp;
+    double src_s[kMaxN];   // h s(t + xi_b dt) of the point source at the time nodes (host)
 };
 
 // lamface[c][j][side][v][f] = sum_i L_side[i] lam[c][v][node(f, j, i)]
@@ -164,7 +164,7 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
             z[t][v] = Qn[v];
             zd[t][v] = 0.0;
         }
-    auto src_term = [&](int b) { return h * ricker(a.t + B->xi[b] * a.dt, a.src_f0, a.src_t0, a.src_amp) * src_phi; };
+    auto src_term = [&](int b) { return a.src_s[b] * src_phi; };
 #pragma unroll 1
     for (int it = 0; it < iters; it++) {
 #pragma unroll
