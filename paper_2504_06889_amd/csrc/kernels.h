@@ -421,16 +421,17 @@ struct PredLds {
     static constexpr size_t bytes = bytes1 > corr ? bytes1 : corr;
 };
 
-// Target occupancy of the predictor (wavefronts per SIMD, one workgroup of at
-// most four wavefronts per CU per wavefront and SIMD): three (at most 168
-// registers per lane) for the lower-format paths, whose iterate rows are FP32,
-// when the LDS holds three workgroups per CU; else two (256 registers) when it
-// holds two.
+// Target occupancy of the predictor (wavefronts per SIMD; a workgroup has at
+// most four wavefronts, one per SIMD): three (at most 168 registers per lane)
+// when the LDS holds three workgroups per CU, else two (256 registers) when it
+// holds two.  The latency of the two barriers per slice needs the third
+// wavefront: the FP64 3-D elastic order-5 kernel spills 124 bytes per lane at
+// this target and still runs 13 % faster than at two.
 template <class Pde, int DIM, int N, int PP>
 struct PredOcc {
     static constexpr size_t lds = PredLds<Pde, DIM, N, PP>::bytes;
     static constexpr bool fits = Shape<DIM, N>::TPB <= 256;
-    static constexpr int waves = !fits ? 1 : (PP != P64 && lds * 3 <= 160 * 1024) ? 3 : (lds * 2 <= 160 * 1024 ? 2 : 1);
+    static constexpr int waves = !fits ? 1 : (lds * 3 <= 160 * 1024) ? 3 : (lds * 2 <= 160 * 1024 ? 2 : 1);
 };
 
 // For a linear flux with cell-constant coefficients and FP64 faces, the face
