@@ -484,10 +484,12 @@ def main():
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "%s-mfma+f64" % head if head != "fp64" else "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: 3-D elastic waves, N=5, 64^3 periodic cells, planar P+S wave, "
-                               "predictor+volume contractions in %s on matrix cores (FP32 accumulate), "
+        "config": {"workload": "%s: 3-D elastic waves, N=5, 64^3 periodic cells, planar P+S wave, %s, "
                                "Picard time operator, averages, flux/corrector and state FP64, "
-                               "C_CFL=%.2f, dt=%.6e" % (sc.name, head, sc.cfl, dt),
+                               "C_CFL=%.2f, dt=%.6e" % (
+                                   sc.name, "all contractions FP64 on the vector ALU" if head == "fp64" else
+                                   "predictor+volume contractions in %s on matrix cores (FP32 accumulate)" % head,
+                                   sc.cfl, dt),
                    "cells": g.ncell, "order": sc.order, "dof_per_step": dof, "picard_iters": I},
         "roofline": r["roofline"],
         "speedup_vs_fp64": r.get("speedup_vs_fp64"),

@@ -107,7 +107,7 @@ struct AdjLayout {
 };
 
 template <int DIM, int N>
-__global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_adjoint(AdjKArgs a) {
+__global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_adjoint(AdjKArgs a) {
     using Sh = Shape<DIM, N>;
     using AL = AdjLayout<DIM, N>;
     using Pde = Acoustic<DIM>;
