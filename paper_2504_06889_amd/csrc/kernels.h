@@ -852,7 +852,9 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
             __syncthreads();
             M.template run<PL::NTILE, NWAVE, F>(Fb, Rb, wave, lane);
             __syncthreads();
-            if (active) {
+            // every slot thread reads its results, so this block and the next
+            // slice's flux writes share one condition; only real cells fold them
+            if (slot) {
                 float rf[V], eta[DIM];
 #pragma unroll
                 for (int v = 0; v < V; v++) rf[v] = 0.0f;
@@ -872,7 +874,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                         }
                     }
                 }
-                sink(rf, eta);
+                if (active) sink(rf, eta);
             }
         };
         // One slice: flux of q_b at every node, the derivative lines and the
