@@ -7,10 +7,13 @@
 //    differentiated (D along x, y, z: in place in FP64 on the vector ALU, or
 //    on the matrix cores in FP32/BF16/FP16 with FP32 accumulation), and the
 //    owner thread folds the divergence into the FP64 Picard update
-//    q_a <- Q - dt sum_b Atau[a][b] R_b (eq. Picard at the nodes).  The
-//    epilogue forms the FP64 time averages, projects them to the 2d faces
-//    (Alg. 1 "expansion") and adds the volume integral to Q.  The fused
-//    variant first runs the previous step's corrector for its cells.
+//    q_a <- Q - dt sum_b Atau[a][b] R_b (eq. Picard at the nodes); for a
+//    linear PDE the Cauchy-Kowalevskaya procedure can replace the iteration
+//    (N slices on the Taylor terms).  The epilogue forms the FP64 time
+//    averages, projects them to the 2d faces (Alg. 1 "expansion") and adds
+//    the volume integral to Q (on the matrix cores for linear PDEs in a
+//    16-bit format).  The fused variant first runs the previous step's
+//    corrector for its cells.
 //  k_corrector: per cell, the Rusanov flux on each face node of its 2d faces
 //    (eq. rusanov_flux; well-balanced form for shallow water) and the face
 //    integral (lift) into Q in FP64.
@@ -1142,10 +1145,6 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     }
 }
 
-// ---------------------------------------------------------------------------
-// Corrector: Riemann solve per face node and face integral (Alg. 1, second
-// traversal).  FP is the face format; FP32 arithmetic when FP != FP64.
-// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // Largest wave speed over all nodes and directions (for eq. CFL_condition).
 // Non-negative doubles order like their bit patterns, so atomicMax on the
