@@ -76,3 +76,27 @@ def test_full_size_step_at_sampled_cells(oracle_mod, name, p):
     print("%s %s: sampled max rel %.3e, rel L2 %.3e" % (name, p, err, rel), flush=True)
     assert np.all(np.isfinite(B))
     assert rel <= TOL[p] and err <= 10 * TOL[p], (rel, err)
+
+
+@pytest.mark.parametrize("p", ["fp64", "fp16"])
+def test_full_size_ck_step_at_sampled_cells(oracle_mod, p):
+    """The Cauchy-Kowalevskaya runs the benchmark reports beside the Picard ones."""
+    sc = inputs.SCENARIOS["elastic3d_n5_64"]
+    print("case ck", sc.name, p, flush=True)
+    o = oracle_mod.Oracle(sc.dim, sc.order, sc.cells, sc.lo, sc.hi, sc.pde, sc.params, predictor="ck")
+    Q0 = sc.initial_state(o.node_coords())
+    o.set_state(Q0)
+    dt = o.max_dt(sc.cfl)
+    ids = _sample_ids(sc.cells, seed=11)
+    ref = o.step_cells(0.0, dt, ids)
+    del o
+    g = gpu_solver(sc, prec=("fp64",) * 3 if p == "fp64" else (p, p, "fp64"))
+    g.set_predictor("ck")
+    g.set_state(Q0)
+    g.step(dt, 1)
+    B = g.get_state()[ids]
+    err = np.abs(B - ref).max() / np.abs(ref).max()
+    rel = np.linalg.norm(B - ref) / np.linalg.norm(ref)
+    print("ck %s: sampled max rel %.3e, rel L2 %.3e" % (p, err, rel), flush=True)
+    assert np.all(np.isfinite(B))
+    assert rel <= TOL[p] and err <= 10 * TOL[p], (rel, err)
