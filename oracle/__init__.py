@@ -43,7 +43,7 @@ class _Config(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("order", ctypes.c_int), ("cells", ctypes.c_int * 3),
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3), ("pde", ctypes.c_int),
                 ("params", ctypes.c_double * 8), ("picard_iters", ctypes.c_int),
-                ("prec", ctypes.c_int * 3), ("predictor", ctypes.c_int)]
+                ("prec", ctypes.c_int * 3), ("predictor", ctypes.c_int), ("storage", ctypes.c_int)]
 
 PREDICTORS = {"picard": 0, "ck": 1}
 
@@ -127,7 +127,7 @@ class Oracle:
     """FP64 CPU ADER-DG on a periodic Cartesian grid (state layout [cell][var][node])."""
 
     def __init__(self, dim, order, cells, lo, hi, pde, params, picard_iters=0,
-                 prec=(FP64, FP64, FP64), predictor="picard"):
+                 prec=(FP64, FP64, FP64), predictor="picard", storage="fp64"):
         c = _Config()
         c.dim, c.order = dim, order
         cells = list(cells) + [1] * (3 - len(cells))
@@ -144,6 +144,8 @@ class Oracle:
             c.prec[i] = PREC_IDS.get(prec[i], prec[i])
         c.predictor = PREDICTORS[predictor]
         self.predictor = predictor
+        c.storage = PREC_IDS.get(storage, storage)
+        self.storage = storage
         self._cfg = c
         self._h = lib().or_create(ctypes.byref(c))
         if not self._h:

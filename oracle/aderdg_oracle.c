@@ -398,6 +398,7 @@ or_solver *or_create(const or_config *cfg)
     if (cfg->dim < 1 || cfg->dim > 3 || cfg->order < 0 || cfg->order + 1 > MAXN) return NULL;
     int V = or_nvars(cfg->pde, cfg->dim);
     if (V <= 0 || V > MAXV) return NULL;
+    if (cfg->storage < OR_FP64 || cfg->storage > OR_FP16) return NULL;
     if (cfg->predictor != OR_PICARD &&
         (cfg->predictor != OR_CK || (cfg->pde != OR_ACOUSTIC && cfg->pde != OR_ELASTIC)))
         return NULL; /* the CK procedure needs a linear flux */
@@ -431,9 +432,19 @@ void or_destroy(or_solver *s)
     free(s);
 }
 
+/* The state as held between traversals: each value rounded to the storage
+ * precision. */
+static void store_round(const or_solver *s, double *Q, size_t count)
+{
+    if (s->c.storage == OR_FP64) return;
+    for (size_t i = 0; i < count; i++) Q[i] = or_round(s->c.storage, Q[i]);
+}
+
 void or_set_state(or_solver *s, const double *Q)
 {
-    memcpy(s->Q, Q, (size_t)s->ncell * s->V * s->S * sizeof(double));
+    const size_t count = (size_t)s->ncell * s->V * s->S;
+    memcpy(s->Q, Q, count * sizeof(double));
+    store_round(s, s->Q, count);
 }
 
 void or_get_state(const or_solver *s, double *Q)
@@ -857,8 +868,10 @@ int or_step(or_solver *s, double t, double dt)
         cell_work w;
         work_alloc(s, &w);
 #pragma omp for schedule(dynamic, 4)
-        for (int64_t c = 0; c < s->ncell; c++)
+        for (int64_t c = 0; c < s->ncell; c++) {
             cell_first_sweep(s, c, t, dt, &w, Qn + c * VS, fq + c * FS, ff + c * FS);
+            store_round(s, Qn + c * VS, VS); /* Q* is stored between the traversals */
+        }
         work_free(&w);
     }
 #pragma omp parallel for schedule(dynamic, 16)
@@ -873,6 +886,7 @@ int or_step(or_solver *s, double t, double dt)
                 bf[1 + 2 * j + side] = ff + nc * FS;
             }
         correct_cell(s, c, dt, bq, bf, Qn + c * VS);
+        store_round(s, Qn + c * VS, VS);
     }
     free(fq);
     free(ff);
@@ -902,6 +916,7 @@ int or_step_cells(const or_solver *s, double t, double dt, int m, const int64_t 
             if (c < 0 || c >= s->ncell) { err = -1; continue; }
             double *Qc = out + (size_t)i * VS;
             cell_first_sweep(s, c, t, dt, &w, Qc, fq, ff);
+            store_round(s, Qc, VS);
             const double *bq[1 + 2 * 3], *bf[1 + 2 * 3];
             for (int k = 0; k < nb; k++) { bq[k] = fq + k * FS; bf[k] = ff + k * FS; }
             for (int j = 0; j < s->d; j++)
@@ -911,6 +926,7 @@ int or_step_cells(const or_solver *s, double t, double dt, int m, const int64_t 
                     cell_first_sweep(s, nc, t, dt, &w, NULL, fq + k * FS, ff + k * FS);
                 }
             correct_cell(s, c, dt, bq, bf, Qc);
+            store_round(s, Qc, VS);
         }
         free(fq);
         free(ff);
@@ -990,7 +1006,7 @@ static void acoustic_flux_transpose(int d, double K, double rho, const double *x
 int or_adjoint_step(or_solver *s, const double *Qn, double t, double dt, const double *lam,
                     double *mu, double *grad)
 {
-    if (s->c.pde != OR_ACOUSTIC || !s->cmat || s->c.predictor != OR_PICARD) return -1;
+    if (s->c.pde != OR_ACOUSTIC || !s->cmat || s->c.predictor != OR_PICARD || s->c.storage != OR_FP64) return -1;
     if (s->c.prec[0] || s->c.prec[1] || s->c.prec[2]) return -1;
     const int n = s->n, S = s->S, V = s->V, d = s->d, F = s->F, I = s->I;
     const size_t VS = (size_t)V * S, FS = (size_t)d * 2 * V * F;

@@ -39,6 +39,11 @@
  * predictor then use FP32-rounded states; face values are stored rounded to
  * the flux format; the lift multiplies format-rounded inputs in FP32.  Time
  * averages, the Picard time operator and all state accumulation stay FP64.
+ *
+ * Storage precision (the paper's fourth control, Sec. 3.1): the persistent
+ * state is held in that format between grid traversals: the state given to
+ * or_set_state, the first sweep's Q* and the corrected state are each rounded
+ * to it (FP32 first, then the format); all arithmetic stays as above.
  */
 #ifndef ADERDG_ORACLE_H
 #define ADERDG_ORACLE_H
@@ -61,6 +66,7 @@ typedef struct {
     int picard_iters; /* 0 -> order + 1 */
     int prec[3];      /* emulated precision: predictor, volume, flux */
     int predictor;    /* OR_PICARD, or OR_CK (linear PDEs without a point source) */
+    int storage;      /* emulated storage precision of the state between traversals */
 } or_config;
 
 typedef struct or_solver {
