@@ -281,13 +281,17 @@ def sweep():
 PAPER_RUNS = [("fp64", ("fp64",) * 3), ("predictor+volume=fp32", ("fp32", "fp32", "fp64")),
               ("flux=fp32", ("fp64", "fp64", "fp32")), ("predictor+volume=bf16", ("bf16", "bf16", "fp64")),
               ("predictor+volume=fp16", ("fp16", "fp16", "fp64")), ("all=fp32", ("fp32",) * 3),
-              ("all=bf16", ("bf16",) * 3), ("all=fp16", ("fp16",) * 3)]
+              ("all=bf16", ("bf16",) * 3), ("all=fp16", ("fp16",) * 3),
+              # every kernel and the stored state in the format (the paper's "all" columns)
+              ("all+storage=fp32", ("fp32",) * 4), ("all+storage=bf16", ("bf16",) * 4),
+              ("all+storage=fp16", ("fp16",) * 4)]
 
 
 def paper_suite():
     """The paper's 2-D scenarios of its mixed-precision study (27^2 cells, order 5, run to
     t_end) with the state in FP64 and the predictor and volume contractions, the face
-    kernels, or all of them in a lower format (the paper's one-kernel-at-a-time design):
+    kernels, or all of them in a lower format (the paper's one-kernel-at-a-time design),
+    and with every kernel and the stored state in the format:
     the L2 error of eq. L2gauss against the interpolant of the exact solution at t_end,
     absolute (as the paper reports it) and relative, the relative L2 difference to the
     FP64 GPU run and, for the lake at rest, the largest spurious momentum."""
@@ -308,10 +312,11 @@ def paper_suite():
         nex = l2(W, g.h, g.d, exact)
         ref, runs = None, {}
         for label, prec in PAPER_RUNS:
-            g.set_precisions(*prec)
+            g.set_precision("storage", prec[3] if len(prec) > 3 else "fp64")
+            g.set_precisions(*prec[:3])
             g.set_state(Q0)
             g.time = 0.0
-            r = {"precisions": dict(zip(("predictor", "volume", "flux"), prec))}
+            r = {"precisions": dict(zip(("predictor", "volume", "flux", "storage"), tuple(prec) + ("fp64",) * (4 - len(prec))))}
             try:
                 g.step(dt, nsteps)
                 st = g.get_state(out=torch.empty(g.shape, dtype=torch.float64, device="cuda"))

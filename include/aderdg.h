@@ -53,7 +53,12 @@ typedef enum { ADERDG_ACOUSTIC = 0, ADERDG_ELASTIC = 1, ADERDG_EULER = 2, ADERDG
  *   VOLUME    - the volume-integral contraction;
  *   FLUX      - face projection, face-value storage, Riemann solve and lift
  *               (the paper's "corrector"; the update Q += dt (...) stays FP64);
- *   STORAGE   - the persistent state: FP64 only (other values: UNSUPPORTED).
+ *   STORAGE   - the persistent state held between traversals (the state
+ *               given to set_state, Q* after the predictor, the corrected
+ *               state) is rounded to that format (FP32 first, then the
+ *               format) each time it is stored; it stays in FP64 containers
+ *               (same layout and footprint); all arithmetic is unchanged.
+ *               Default FP64.
  * In a lower precision the contraction inputs (data and matrix) are rounded
  * to that format (round-to-nearest-even) and the products are accumulated in
  * FP32 (matrix cores for PREDICTOR and VOLUME); the Picard time operator, the
@@ -112,8 +117,10 @@ aderdg_status aderdg_set_material(aderdg_solver *s, const double *c, int is_devi
  * adjoint and point sources need PICARD.                                      */
 aderdg_status aderdg_set_predictor(aderdg_solver *s, int kind);
 
-/* Select the precision of one kernel's contractions (see aderdg_kernel).
- * Errors: INVALID (unknown kernel/precision), UNSUPPORTED (STORAGE != FP64).  */
+/* Select the precision of one kernel's contractions, or the storage precision
+ * of the state (see aderdg_kernel).  Setting STORAGE rounds the state held now
+ * to it.  Errors: INVALID (unknown kernel/precision), UNSUPPORTED (predictor
+ * format not built), DEVICE.  The adjoint needs FP64 storage.                */
 aderdg_status aderdg_set_precision(aderdg_solver *s, int kernel, int prec);
 
 /* Largest admissible time step of eq. CFL_condition,

@@ -40,6 +40,10 @@ const KernelSet *find_kernels(int pde, int dim, int order) {
 // ---------------------------------------------------------------------------
 __global__ void k_fill_u64(unsigned long long *p, unsigned long long v) { *p = v; }
 __global__ void k_fill_i32(int *p, int v) { *p = v; }
+// Round the held state to its storage precision, in place.
+__global__ __launch_bounds__(256) void k_round_state(double *Q, long n, int sp) {
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) Q[i] = round_q(Q[i], sp);
+}
 
 __global__ __launch_bounds__(256) void k_nonfinite(const double *x, long n, int *flag) {
     int bad = 0;
@@ -240,19 +244,28 @@ aderdg_status aderdg_destroy(aderdg_solver *s) {
     return ADERDG_OK;
 }
 
+static long grid256(long n) {
+    const long g = (n + 255) / 256;
+    return g < 8192 ? g : 8192;
+}
+
+// Round the held state to the storage precision (nothing to do in FP64).
+static void round_state(aderdg_solver *s) {
+    const int sp = s->prec[ADERDG_K_STORAGE];
+    if (sp != ADERDG_FP64)
+        hipLaunchKernelGGL(k_round_state, dim3(grid256(state_elems(s))), dim3(256), 0, s->stream, s->dQ,
+                           state_elems(s), sp);
+}
+
 aderdg_status aderdg_set_state(aderdg_solver *s, const double *Q, int is_device) {
     if (!s) return ADERDG_E_INVALID;
     if (!Q) FAIL(s, ADERDG_E_INVALID, "null state pointer");
     const size_t bytes = sizeof(double) * state_elems(s);
-    if (is_device) {
-        HIPC(s, hipMemcpyAsync(s->dQ, Q, bytes, hipMemcpyDeviceToDevice, s->stream));
-    } else {
-        HIPC(s, hipMemcpyAsync(s->dQ, Q, bytes, hipMemcpyHostToDevice, s->stream));
-        HIPC(s, hipStreamSynchronize(s->stream));
-    }
+    HIPC(s, hipMemcpyAsync(s->dQ, Q, bytes, is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
+    round_state(s);
+    if (!is_device) HIPC(s, hipStreamSynchronize(s->stream));
     return ADERDG_OK;
 }
-
 static aderdg_status check_finite(aderdg_solver *s, const double *x, long count, bool *ok) {
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, s->stream, s->dFlag, 0);
     long g = (count + 255) / 256;
@@ -305,7 +318,13 @@ aderdg_status aderdg_set_predictor(aderdg_solver *s, int kind) {
 aderdg_status aderdg_set_precision(aderdg_solver *s, int kernel, int prec) {
     if (!s) return ADERDG_E_INVALID;
     if (kernel < 0 || kernel > 3 || prec < 0 || prec > 3) FAIL(s, ADERDG_E_INVALID, "unknown kernel or precision");
-    if (kernel == ADERDG_K_STORAGE && prec != ADERDG_FP64) FAIL(s, ADERDG_E_UNSUPPORTED, "the state is stored in FP64");
+    if (kernel == ADERDG_K_STORAGE) {
+        // the held state is rounded to the new storage precision
+        s->prec[kernel] = prec;
+        round_state(s);
+        HIPC(s, hipGetLastError());
+        return ADERDG_OK;
+    }
     if (kernel == ADERDG_K_PREDICTOR && !s->ks->pred[prec])
         FAIL(s, ADERDG_E_UNSUPPORTED, "predictor precision %d not built for this (pde, dim, order)", prec);
     s->prec[kernel] = prec;
@@ -369,6 +388,7 @@ static StepArgs step_args(aderdg_solver *s, double dt, double t) {
     a.flux_prec = s->prec[ADERDG_K_FLUX];
     a.iters = s->iters;
     a.ck = s->predictor == ADERDG_CK;
+    a.store_prec = s->prec[ADERDG_K_STORAGE];
     a.write_state = 1;
     a.src_cell = s->src_cell;
     a.src_phi = s->dSrcPhi;
@@ -568,6 +588,7 @@ static aderdg_status step_adjoint(aderdg_solver *s, double dt, double t, const d
     if (s->prec[ADERDG_K_PREDICTOR] || s->prec[ADERDG_K_VOLUME] || s->prec[ADERDG_K_FLUX])
         FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint is FP64 only");
     if (s->predictor != ADERDG_PICARD) FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint differentiates the Picard predictor");
+    if (s->prec[ADERDG_K_STORAGE] != ADERDG_FP64) FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint needs the state in FP64");
     AdjointArgs a{};
     a.pred = s->ks->pred[0];
     a.cfg_pde = s->cfg.pde;

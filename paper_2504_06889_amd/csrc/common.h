@@ -75,6 +75,17 @@ __device__ __forceinline__ float widen(__hip_bfloat16 x) { return __bfloat162flo
 __device__ __forceinline__ float widen(_Float16 x) { return (float)x; }
 __device__ __forceinline__ double widen(double x) { return x; }
 
+// Storage precision of the persistent state (Prec SP): the state is held in
+// FP64 containers, each value rounded to the format (FP32 first, then the
+// format, nearest-even) whenever it is stored between traversals.
+__device__ __forceinline__ double round_q(double x, int sp) {
+    if (sp == P64) return x;
+    const float f = (float)x;
+    if (sp == P32) return (double)f;
+    if (sp == PBF16) return (double)widen(round_to<PBF16>(f));
+    return (double)widen(round_to<PF16>(f));
+}
+
 // Face-value storage per FLUX precision
 template <int P> struct FaceT { using T = typename Store<P>::T; };
 

@@ -40,6 +40,7 @@ struct StepArgs {
     int iters;            // Picard iterations
     int write_state;      // 0: only the face data is produced (Q untouched)
     int ck;               // 1: Cauchy-Kowalevskaya predictor (linear PDEs, no source)
+    int store_prec;       // storage precision of Q (Prec): stored values are rounded to it
     long src_cell;        // -1: no source
     const double *src_phi;
     // point source: h s(t + xi_b dt) at the n time nodes and the time average
@@ -564,7 +565,8 @@ __device__ __forceinline__ void correct_block(const StepArgs &a, const void *fac
                 }
             }
         }
-        qnew[v] = active ? fma(a.sigma, dq, qs[v]) : 1.0;
+        // the corrected state as stored in the storage precision
+        qnew[v] = active ? round_q(fma(a.sigma, dq, qs[v]), a.store_prec) : 1.0;
     }
 }
 
@@ -585,7 +587,6 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) void k_corrector(StepArgs a) 
     const int cb = tid / S, s = tid % S;
     const long cell = cell0 + cb;
     if (cb < CPB && cell < a.ncell) {
-#pragma unroll
         for (int v = 0; v < V; v++) a.Q[(cell * V + v) * S + s] = qnew[v];
     }
 }
@@ -1140,7 +1141,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
             double qn = Qn[v] + a.sigma * vol[v];
             if constexpr (Pde::kNCP) qn -= a.sigma * nbar[v];
             if (v == 0 && src_here) qn += a.dt * sbar * src_phi;
-            a.Q[(cell * V + v) * S + s] = qn;
+            a.Q[(cell * V + v) * S + s] = round_q(qn, a.store_prec);  // Q* in the storage precision
         }
     }
 }

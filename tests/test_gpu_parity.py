@@ -232,8 +232,8 @@ def test_invalid_and_unsupported_requests():
     sc, _, _ = _case("acoustic2d_n2")
     g = gpu_solver(sc, sc.cells)
     with pytest.raises(AderdgError) as e:
-        g.set_precision("storage", "fp32")
-    assert e.value.code == -2
+        g.set_precision("storage", 7)
+    assert e.value.code == -1
     with pytest.raises(AderdgError) as e:
         g.set_precision("predictor", "fp32")  # not built for acoustic 2-D N=2
     assert e.value.code == -2
