@@ -233,13 +233,16 @@ class Oracle:
 
     def adjoint_step(self, Qn, t, dt, lam, grad):
         """Reverse-mode adjoint of one step (acoustics with material): returns
-        (J^T lam, grad + d<lam, step(Qn)>/dc).  Qn is the state at the step start."""
+        (J^T lam, grad + d<lam, step(Qn)>/dc).  Qn is the state at the step start.
+        With the predictor and volume precisions both below FP64 (flux FP64) the
+        transposed contractions run in those formats (emulated, FP32 accumulation)."""
         Qn = np.ascontiguousarray(Qn, dtype=np.float64)
         lam = np.ascontiguousarray(lam, dtype=np.float64)
         mu = np.zeros_like(lam)
         g = np.array(grad, dtype=np.float64, copy=True)
         if lib().or_adjoint_step(self._h, _ptr(Qn), t, dt, _ptr(lam), _ptr(mu), _ptr(g)) != 0:
-            raise ValueError("adjoint needs acoustics with a material and FP64")
+            raise ValueError("adjoint needs acoustics with a material, the Picard predictor, "
+                             "FP64 storage and flux, and predictor and volume both FP64 or both lower")
         return mu, g
 
     def point_weights(self, x):

@@ -993,6 +993,17 @@ int or_num_threads(void)
 /* modulus K = rho c^2 enters through F_j(q) = (K v_j, p/rho e_j).           */
 /*   mu   <- (d Q^{n+1} / d Q^n)^T lam                                       */
 /*   grad += d <lam, Q^{n+1}> / d c   (one entry per cell)                    */
+/*                                                                            */
+/* Mixed precision (predictor and volume formats both below FP64, flux FP64): */
+/* the recomputed Picard iterates follow the forward step's emulation, and    */
+/* each transposed contraction runs in the format of the forward contraction */
+/* it transposes -- D_j^T of the Picard iterations in the predictor's format, */
+/* Kxi^T of the volume integral in the volume format -- with the inputs       */
+/* rounded to the format and FP32 accumulation (contract()).  The time        */
+/* operator, the pointwise A_j^T, the face terms and every accumulation into  */
+/* mu and grad stay FP64.  It approximates the exact adjoint to the format's  */
+/* level; it is not the transpose of the rounded forward map, which is not    */
+/* linear.                                                                    */
 /* ------------------------------------------------------------------------ */
 
 /* y = A_j^T x at one node: A_j q = (K q[1+j], q[0]/rho e_j) */
@@ -1007,7 +1018,8 @@ int or_adjoint_step(or_solver *s, const double *Qn, double t, double dt, const d
                     double *mu, double *grad)
 {
     if (s->c.pde != OR_ACOUSTIC || !s->cmat || s->c.predictor != OR_PICARD || s->c.storage != OR_FP64) return -1;
-    if (s->c.prec[0] || s->c.prec[1] || s->c.prec[2]) return -1;
+    const int pp = s->c.prec[0], pv = s->c.prec[1];
+    if (s->c.prec[2] != OR_FP64 || (pp == OR_FP64) != (pv == OR_FP64)) return -1;
     const int n = s->n, S = s->S, V = s->V, d = s->d, F = s->F, I = s->I;
     const size_t VS = (size_t)V * S, FS = (size_t)d * 2 * V * F;
     const double rho = s->c.params[0], sigma = dt / s->h, inv_h = 1.0 / s->h;
@@ -1087,7 +1099,7 @@ int or_adjoint_step(or_solver *s, const double *Qn, double t, double dt, const d
             double Kbar = 0.0;
             /* volume: Qstar += sigma sum_j Kxi (x)_j fbar_j */
             for (int j = 0; j < d; j++) {
-                apply_dir(s, Kxit, j, lc, fbb + (size_t)j * VS, V, OR_FP64);
+                apply_dir(s, Kxit, j, lc, fbb + (size_t)j * VS, V, pv);
                 for (size_t i = 0; i < VS; i++) fbb[(size_t)j * VS + i] *= sigma;
             }
             memset(qbb, 0, sizeof(double) * VS);
@@ -1157,7 +1169,7 @@ int or_adjoint_step(or_solver *s, const double *Qn, double t, double dt, const d
                 for (int b = 0; b < n; b++)
                     for (int j = 0; j < d; j++) {
                         /* R_b = (1/h) sum_j D_j A_j q_b */
-                        apply_dir(s, Dt, j, Rb + b * VS, Y, V, OR_FP64);
+                        apply_dir(s, Dt, j, Rb + b * VS, Y, V, pp);
                         for (int sn = 0; sn < S; sn++) {
                             double x[MAXV], y[MAXV];
                             for (int v = 0; v < V; v++) x[v] = inv_h * Y[v * S + sn];
