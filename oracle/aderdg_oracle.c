@@ -1001,12 +1001,30 @@ int or_num_threads(void)
 /* Kxi^T of the volume integral in the volume format -- with the inputs       */
 /* rounded to the format and FP32 accumulation (contract()).  The time        */
 /* operator, the pointwise A_j^T, the face terms and every accumulation into  */
-/* mu and grad stay FP64.  It approximates the exact adjoint to the format's  */
-/* level; it is not the transpose of the rounded forward map, which is not    */
-/* linear.                                                                    */
+/* mu and grad stay FP64.  As the adjoint is linear in the incoming adjoint, */
+/* each cell's contraction inputs are multiplied by a power of two before    */
+/* the rounding and the results divided by it (exact operations), the power  */
+/* chosen from the largest incoming adjoint value of the cell (lam and the   */
+/* face terms G) so that it lands in [2^7, 2^8): the small adjoint values of */
+/* a misfit sweep then keep the format's precision instead of underflowing   */
+/* (FP16's smallest normal is 2^-14).  It approximates the exact adjoint to  */
+/* the format's level; it is not the transpose of the rounded forward map,   */
+/* which is not linear.                                                       */
 /* ------------------------------------------------------------------------ */
 
 /* y = A_j^T x at one node: A_j q = (K q[1+j], q[0]/rho e_j) */
+#define ADJ_SCALE_EXP 8 /* scaled largest incoming adjoint value in [2^7, 2^8) */
+
+/* apply_dir on sc * X (rounded in format p), result divided by sc; tmp: nv*S */
+static void apply_dir_scaled(const or_solver *s, const double *M, int j, const double *X, double *out,
+                             int nv, int p, double sc, double *tmp)
+{
+    const size_t m = (size_t)nv * s->S;
+    for (size_t i = 0; i < m; i++) tmp[i] = sc * X[i];
+    apply_dir(s, M, j, tmp, out, nv, p);
+    for (size_t i = 0; i < m; i++) out[i] /= sc;
+}
+
 static void acoustic_flux_transpose(int d, double K, double rho, const double *x, int j, double *y)
 {
     for (int v = 0; v <= d; v++) y[v] = 0.0;
@@ -1091,15 +1109,41 @@ int or_adjoint_step(or_solver *s, const double *Qn, double t, double dt, const d
         double *rho_n = (double *)malloc(sizeof(double) * n * VS);
         double *Rb = (double *)malloc(sizeof(double) * n * VS);
         double *Y = (double *)malloc(sizeof(double) * VS);
+        double *T = (double *)malloc(sizeof(double) * VS);
         double *Gb = (double *)malloc(sizeof(double) * V * F);
 #pragma omp for schedule(dynamic, 1)
         for (int64_t c = 0; c < s->ncell; c++) {
             const double *lc = lam + c * VS;
             const double K = rho * s->cmat[c] * s->cmat[c];
             double Kbar = 0.0;
+            /* scale of the cell's contraction inputs (mixed precision) */
+            double sc = 1.0;
+            if (pp != OR_FP64) {
+                double m = 0.0;
+                for (size_t i = 0; i < VS; i++) m = fmax(m, fabs(lc[i]));
+                for (int j = 0; j < d; j++) {
+                    int st = stride_of(j, n);
+                    for (int side = 0; side < 2; side++) {
+                        int64_t nb = neighbour(s, c, j, side ? +1 : -1);
+                        const double *lL = lam + (side ? c : nb) * VS, *lR = lam + (side ? nb : c) * VS;
+                        for (int v = 0; v < V; v++)
+                            for (int sn = 0; sn < S; sn++) {
+                                if (coord(sn, j, n) != 0) continue;
+                                double g = sigma * (contract(n, s->L0, lR + v * S + sn, st, OR_FP64) -
+                                                    contract(n, s->L1, lL + v * S + sn, st, OR_FP64));
+                                m = fmax(m, fabs(g));
+                            }
+                    }
+                }
+                if (m > 0.0) {
+                    int e;
+                    frexp(m, &e);
+                    sc = ldexp(1.0, ADJ_SCALE_EXP - e);
+                }
+            }
             /* volume: Qstar += sigma sum_j Kxi (x)_j fbar_j */
             for (int j = 0; j < d; j++) {
-                apply_dir(s, Kxit, j, lc, fbb + (size_t)j * VS, V, pv);
+                apply_dir_scaled(s, Kxit, j, lc, fbb + (size_t)j * VS, V, pv, sc, T);
                 for (size_t i = 0; i < VS; i++) fbb[(size_t)j * VS + i] *= sigma;
             }
             memset(qbb, 0, sizeof(double) * VS);
@@ -1169,7 +1213,7 @@ int or_adjoint_step(or_solver *s, const double *Qn, double t, double dt, const d
                 for (int b = 0; b < n; b++)
                     for (int j = 0; j < d; j++) {
                         /* R_b = (1/h) sum_j D_j A_j q_b */
-                        apply_dir(s, Dt, j, Rb + b * VS, Y, V, pp);
+                        apply_dir_scaled(s, Dt, j, Rb + b * VS, Y, V, pp, sc, T);
                         for (int sn = 0; sn < S; sn++) {
                             double x[MAXV], y[MAXV];
                             for (int v = 0; v < V; v++) x[v] = inv_h * Y[v * S + sn];
@@ -1184,7 +1228,7 @@ int or_adjoint_step(or_solver *s, const double *Qn, double t, double dt, const d
             }
             grad[c] += Kbar * 2.0 * rho * s->cmat[c];
         }
-        free(qbb); free(fbb); free(rho_a); free(rho_n); free(Rb); free(Y); free(Gb);
+        free(qbb); free(fbb); free(rho_a); free(rho_n); free(Rb); free(Y); free(T); free(Gb);
     }
     free(iters);
     free(qbar);
