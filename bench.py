@@ -147,12 +147,14 @@ def cpu_baseline(sc, seconds=12.0, cells=8):
                       "(%d cells, same order and cell size), %.1f s" % (steps, cells, o.ncell, el)}
 
 
-def adjoint_bench(steps=None, checkpoint=None, fd=True):
+def adjoint_bench(steps=None, checkpoint=None, fd=True, mixed=("fp16", "bf16")):
     """Receiver-misfit gradient on the adjoint configuration: 3-D acoustics N=5,
     64^3 cells on [0,20]^3, log-normal per-cell sound speed (mean 1.5, sigma 0.2,
     seed 0), Ricker source f0=5 at the centre of cell (32,32,32), 64 receivers,
     200 steps, checkpoint every 20.  Times the forward misfit and the backward
-    (adjoint) sweep and checks the gradient against central differences."""
+    (adjoint) sweep in FP64 and checks the gradient against central differences;
+    then the same with the predictor and volume contractions of the forward and
+    of the adjoint in each format of `mixed`, against the FP64 gradient."""
     import torch
     from paper_2504_06889_amd import adjoint as adj
     from paper_2504_06889_amd import inputs
@@ -175,21 +177,24 @@ def adjoint_bench(steps=None, checkpoint=None, fd=True):
     adj.record(g, c, Q0, dt, steps)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    cg = c.clone().requires_grad_(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    J = adj.misfit(cg, g, Q0, dt, steps, data, checkpoint)
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    J.backward()
-    torch.cuda.synchronize()
-    t_bwd = time.perf_counter() - t0
-    grad = cg.grad
+
+    def gradient():
+        cg = c.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = adj.misfit(cg, g, Q0, dt, steps, data, checkpoint)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        return float(J.detach()), cg.grad, t_fwd, time.perf_counter() - t0
+
+    J, grad, t_fwd, t_bwd = gradient()
     out = {"workload": "adjoint_acoustic3d_n5_64: 3-D acoustics N=5, 64^3 cells, %d steps, checkpoint %d, "
                        "64 receivers, Ricker f0=5, dt=%.6e" % (steps, checkpoint, dt),
            "forward_ms": 1e3 * t_fwd, "forward_plain_ms": 1e3 * t_plain, "backward_ms": 1e3 * t_bwd,
-           "adjoint_over_forward": t_bwd / t_fwd, "misfit": float(J.detach()), "grad_norm": float(grad.norm())}
+           "adjoint_over_forward": t_bwd / t_fwd, "misfit": J, "grad_norm": float(grad.norm())}
     if fd:
         rng = np.random.default_rng(7)
         dc = torch.from_numpy(rng.standard_normal(g.ncell)).cuda()
@@ -201,6 +206,20 @@ def adjoint_bench(steps=None, checkpoint=None, fd=True):
         ad = float(grad @ dc)
         out.update({"fd_directional": fdv, "adjoint_directional": ad, "fd_rel_err": abs(fdv - ad) / abs(fdv),
                     "fd_tolerance": 1e-6})
+    runs = []
+    for p in mixed:
+        g.set_precisions(p, p, "fp64")
+        Jp, gp, tf, tb = gradient()
+        runs.append({"predictor_volume": p, "forward_ms": 1e3 * tf, "backward_ms": 1e3 * tb,
+                     "adjoint_over_forward": tb / tf, "backward_speedup_vs_fp64": t_bwd / tb,
+                     "misfit_rel_err": abs(Jp - J) / abs(J),
+                     "grad_rel_err": float((gp - grad).norm() / grad.norm())})
+        print("adjoint %s: %.1f ms forward, %.1f ms backward, gradient rel err %.2e vs FP64" % (
+            p, runs[-1]["forward_ms"], runs[-1]["backward_ms"], runs[-1]["grad_rel_err"]),
+            file=sys.stderr, flush=True)
+    g.set_precisions("fp64", "fp64", "fp64")
+    if runs:
+        out["mixed"] = runs
     g.close()
     return out
 

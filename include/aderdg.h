@@ -152,13 +152,22 @@ aderdg_status aderdg_set_receivers(aderdg_solver *s, int nrec, const double *xyz
  * out[nrec] (host or device).                                               */
 aderdg_status aderdg_read_receivers(aderdg_solver *s, double *out, int is_device);
 
-/* Adjoint of one step (acoustics with a per-cell material, FP64).  Given the
+/* Adjoint of one step (acoustics with a per-cell material).  Given the
  * state Qn (device, the state at the start of the step), the adjoint lam
  * (device, state layout) of the state after the step, it overwrites lam with
  * the adjoint of Qn (the transpose of the step applied to lam) and adds to
  * grad (device, one double per cell) the derivative of <lam_in, step(Qn)>
  * with respect to each cell's sound speed.  The solver's own state is not
- * used or changed; dt must equal the forward step.                          */
+ * used or changed; dt must equal the forward step.
+ * Precision: with PREDICTOR and VOLUME in FP64 everything is FP64; with both
+ * in lower formats (dim 2 order 3, dim 3 orders 2 and 5) each transposed
+ * contraction runs in the format of the forward one -- the derivative passes
+ * of the Picard iterations in the predictor's format, the volume operator in
+ * the volume format -- on rounded inputs with FP32 accumulation, everything
+ * else in FP64: the exact adjoint to the format's level.
+ * Errors: INVALID (null pointer, dt <= 0), UNSUPPORTED (not acoustics with a
+ * material, CK predictor, storage or FLUX other than FP64, one of PREDICTOR
+ * and VOLUME in FP64 and the other not, (dim, order) not built), OOM, DEVICE. */
 aderdg_status aderdg_step_adjoint(aderdg_solver *s, double dt, double t, const double *Qn_dev,
                                   double *lam_dev, double *grad_dev);
 

@@ -8,7 +8,7 @@
 namespace aderdg {
 
 struct AdjointArgs {
-    void (*pred)(const StepArgs &, hipStream_t);  // forward FP64 predictor of this shape
+    void (*pred)(const StepArgs &, hipStream_t);  // forward predictor of this shape in the predictor format
     int cfg_pde, dim, order;
     long ncell;
     int cells[3];
@@ -24,6 +24,7 @@ struct AdjointArgs {
     const double *src_phi;
     double src_f0, src_t0, src_amp;
     double src_s[kMaxN], src_bar;  // the forward predictor's source values (StepArgs)
+    int prec_pred, prec_vol;       // contraction formats (Prec): both P64, or both lower
 };
 
 // Device work buffers owned by a solver for the adjoint.

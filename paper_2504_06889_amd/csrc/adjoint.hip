@@ -3,7 +3,9 @@
 //   1. k_lamface:   face restrictions L0^T lam, L1^T lam of the incoming adjoint;
 //   2. k_predictor: the forward step's face data from Qn (state untouched);
 //   3. k_adjoint:   per cell, Rusanov/face/volume adjoints, tangent predictor for
-//                   the material derivative, transposed Picard iterations.
+//                   the material derivative, transposed Picard iterations; the
+//                   FP64 kernel, or the mixed-precision one when the predictor
+//                   and volume contractions run in lower formats.
 #include <map>
 #include <utility>
 
@@ -36,7 +38,7 @@ void receivers_adjoint(double *lam, int V, int S, int n, int dim, int nrec, cons
 using LamFaceFn = void (*)(const double *, double *, long, const DevBasis *, hipStream_t);
 using AdjFn = void (*)(const AdjKArgs &, hipStream_t);
 
-template <int DIM, int N>
+template <int DIM, int N, int PP = P64>
 struct AdjInstance {
     static void lamface(const double *lam, double *out, long ncell, const DevBasis *B, hipStream_t st) {
         const long total = ncell * DIM * 2 * (1 + DIM) * Shape<DIM, N>::F;
@@ -46,18 +48,31 @@ struct AdjInstance {
     }
     static void adjoint(const AdjKArgs &a, hipStream_t st) {
         using Sh = Shape<DIM, N>;
-        hipLaunchKernelGGL((k_adjoint<DIM, N>), dim3((a.ncell + Sh::CPB - 1) / Sh::CPB), dim3(Sh::TPB), 0, st, a);
+        hipLaunchKernelGGL((k_adjoint<DIM, N, PP>), dim3((a.ncell + Sh::CPB - 1) / Sh::CPB), dim3(Sh::TPB), 0, st,
+                           a);
     }
 };
 
-static const std::map<std::pair<int, int>, std::pair<LamFaceFn, AdjFn>> &adj_table() {
-    static const std::map<std::pair<int, int>, std::pair<LamFaceFn, AdjFn>> t = {
-        {{2, 1}, {&AdjInstance<2, 1>::lamface, &AdjInstance<2, 1>::adjoint}},
-        {{2, 2}, {&AdjInstance<2, 2>::lamface, &AdjInstance<2, 2>::adjoint}},
-        {{2, 3}, {&AdjInstance<2, 3>::lamface, &AdjInstance<2, 3>::adjoint}},
-        {{3, 1}, {&AdjInstance<3, 1>::lamface, &AdjInstance<3, 1>::adjoint}},
-        {{3, 2}, {&AdjInstance<3, 2>::lamface, &AdjInstance<3, 2>::adjoint}},
-        {{3, 5}, {&AdjInstance<3, 5>::lamface, &AdjInstance<3, 5>::adjoint}},
+struct AdjFns {
+    LamFaceFn lamface;
+    AdjFn by_prec[4];  // by predictor format; null where no mixed forward predictor is built
+};
+
+template <int DIM, int N>
+static AdjFns fp64_only() {
+    return {&AdjInstance<DIM, N>::lamface, {&AdjInstance<DIM, N>::adjoint, nullptr, nullptr, nullptr}};
+}
+template <int DIM, int N>
+static AdjFns all_formats() {
+    return {&AdjInstance<DIM, N>::lamface,
+            {&AdjInstance<DIM, N>::adjoint, &AdjInstance<DIM, N, P32>::adjoint, &AdjInstance<DIM, N, PBF16>::adjoint,
+             &AdjInstance<DIM, N, PF16>::adjoint}};
+}
+
+static const std::map<std::pair<int, int>, AdjFns> &adj_table() {
+    static const std::map<std::pair<int, int>, AdjFns> t = {
+        {{2, 1}, fp64_only<2, 1>()},   {{2, 2}, fp64_only<2, 2>()},   {{2, 3}, all_formats<2, 3>()},
+        {{3, 1}, fp64_only<3, 1>()},   {{3, 2}, all_formats<3, 2>()}, {{3, 5}, all_formats<3, 5>()},
     };
     return t;
 }
@@ -78,6 +93,11 @@ int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::stri
         msg = "adjoint not built for this (dim, order)";
         return ADERDG_E_UNSUPPORTED;
     }
+    const AdjFn adj = (a.prec_pred >= P64 && a.prec_pred <= PF16) ? it->second.by_prec[a.prec_pred] : nullptr;
+    if (!adj) {
+        msg = "mixed-precision adjoint not built for this (dim, order)";
+        return ADERDG_E_UNSUPPORTED;
+    }
     const int V = 1 + a.dim;
     int F = 1;
     for (int i = 1; i < a.dim; i++) F *= a.order + 1;
@@ -87,7 +107,7 @@ int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::stri
         return ADERDG_E_OOM;
     }
     // 1. face restrictions of the incoming adjoint
-    it->second.first(a.lam, (double *)w.lamface, a.ncell, a.B, st);
+    it->second.lamface(a.lam, (double *)w.lamface, a.ncell, a.B, st);
     // 2. forward face data of this step (unless the caller kept them)
     const void *fwd = a.fwdface ? a.fwdface : w.fwdface;
     if (!a.fwdface) {
@@ -103,7 +123,7 @@ int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::stri
         f.sigma = a.sigma;
         f.t = a.t;
         f.h = 1.0 / a.inv_h;
-        f.vol_prec = 0;
+        f.vol_prec = a.prec_vol;
         f.flux_prec = 0;
         f.iters = a.iters;
         f.write_state = 0;
@@ -132,7 +152,8 @@ int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::stri
     k.src_cell = a.src_cell;
     k.src_phi = a.src_phi;
     for (int b = 0; b < kMaxN; b++) k.src_s[b] = a.src_s[b];
-    it->second.second(k, st);
+    k.pv = a.prec_vol;
+    adj(k, st);
     if (hipGetLastError() != hipSuccess) {
         msg = "adjoint kernel launch failed";
         return ADERDG_E_DEVICE;

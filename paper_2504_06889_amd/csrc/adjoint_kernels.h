@@ -15,6 +15,21 @@
 // cell's time averages; the Rusanov speed s = max(c_L, c_R) adds
 // -1/2 <G_adj, q+ - q-> ds/dK_c on each face where c is the larger speed
 // (ties go to the left cell).
+//
+// Mixed precision (k_adjoint<.., true>): the line buffer holds FP32 and each
+// transposed contraction runs in the format of the forward contraction it
+// transposes -- the derivative passes of the recomputed and of the transposed
+// Picard iterations in the predictor's format, the transposed volume operator
+// in the volume format -- with the inputs rounded to the format and FP32
+// accumulation.  The time operator, the pointwise A_j^T, the face terms and
+// every accumulation into the outgoing adjoint and the gradient stay FP64.
+// The adjoint is linear in the incoming adjoint, so each cell multiplies its
+// contraction inputs by a power of two (and the results by its inverse: both
+// exact) that brings the cell's largest incoming adjoint value, over lam and
+// the face terms G, into [2^7, 2^8): the small adjoint values of a misfit
+// sweep keep the format's precision instead of underflowing (FP16's smallest
+// normal is 2^-14), and the headroom below FP16's largest value covers the
+// growth through the transposed iterations.
 #pragma once
 
 #include "kernels.h"
@@ -36,6 +51,7 @@ struct AdjKArgs {
     long src_cell;
     const double *src_phi;
     double src_s[kMaxN];   // h s(t + xi_b dt) of the point source at the time nodes (host)
+    int pv;                // volume contraction format (Prec) of the mixed kernel
 };
 
 // lamface[c][j][side][v][f] = sum_i L_side[i] lam[c][v][node(f, j, i)]
@@ -64,19 +80,20 @@ __global__ __launch_bounds__(256) void k_lamface(const double *lam, double *out,
     }
 }
 
-// In-place position-major FP64 line pass over the lines line_of(L), L < nl:
-// X[i][line] <- sum_k M(i,k) X[k][line] with M(i,k) = T ? Mat[k][i] : Mat[i][k].
-template <int n, bool T, class MT, class LineOf>
-__device__ __forceinline__ void lines_inplace(double *X, int nl, int NLP, MT Mat, LineOf line_of, int tid,
+// In-place position-major line pass over the lines line_of(L), L < nl:
+// X[i][line] <- sum_k M(i,k) X[k][line] with M(i,k) = T ? Mat[k][i] : Mat[i][k],
+// accumulated in the element type of X (FP64, or FP32 on format-rounded inputs).
+template <int n, bool T, class XT, class MT, class LineOf>
+__device__ __forceinline__ void lines_inplace(XT *X, int nl, int NLP, MT Mat, LineOf line_of, int tid,
                                               int nthreads) {
     for (int L = tid; L < nl; L += nthreads) {
         const int Ln = line_of(L);
-        double x[n];
+        XT x[n];
 #pragma unroll
         for (int k = 0; k < n; k++) x[k] = X[k * NLP + Ln];
 #pragma unroll
         for (int i = 0; i < n; i++) {
-            double y = 0.0;
+            XT y = 0;
 #pragma unroll
             for (int k = 0; k < n; k++) y = fma(T ? Mat[k][i] : Mat[i][k], x[k], y);
             X[i * NLP + Ln] = y;
@@ -84,18 +101,58 @@ __device__ __forceinline__ void lines_inplace(double *X, int nl, int NLP, MT Mat
     }
 }
 
+// Pitch of the FP32 line buffer: as for FP64 rows, but 32-bit reads and
+// writes are served 32 lanes at a time on 32 four-byte banks (conflict when
+// two lanes' floats agree mod 32).
+template <int n, int DIM, int NZ, int CPB, int TPB>
+struct Fp32Pitch {
+    using P64 = Fp64Pitch<n, DIM, NZ, CPB, TPB>;
+    static constexpr int NL = P64::NL;
+    static constexpr int cost(const typename P64::Lanes &L, int P) {
+        int c = 0;
+        for (int w = 0; w < TPB / 64; w++)
+            for (int j = 0; j < DIM; j++)
+                for (int g = 0; g < 2; g++) {
+                    int cnt[32] = {};
+                    int mx = 0;
+                    for (int l = w * 64 + 32 * g; l < w * 64 + 32 * g + 32; l++) {
+                        if (L.k[l][j] < 0) continue;
+                        const int b = (L.k[l][j] * P + L.base[l][j]) & 31;
+                        mx = ++cnt[b] > mx ? cnt[b] : mx;
+                    }
+                    c += mx > 1 ? mx - 1 : 0;
+                }
+        return c;
+    }
+    static constexpr int best() {
+        const typename P64::Lanes L = P64::lanes();
+        int bp = NL | 1, bc = cost(L, NL | 1);
+        for (int P = NL; P < NL + 32; P++) {
+            const int c = cost(L, P);
+            if (c < bc) {
+                bc = c;
+                bp = P;
+            }
+        }
+        return bp;
+    }
+    static constexpr int value = best();
+};
+
 // Line slots per direction j and cell: 0: F_j[0] = K v_j, 1: F_j[1+j] = p/rho
 // (the only non-zero components of the acoustic flux), 2, 3: their
 // K-tangents.  The adjoint passes use slots 0 and 1.
-template <int DIM, int N>
+template <int DIM, int N, bool MX>
 struct AdjLayout {
     using Sh = Shape<DIM, N>;
+    using XT = typename std::conditional<MX, float, double>::type;  // line buffer element
     static constexpr int n = Sh::n, F = Sh::F, CPB = Sh::CPB, S = Sh::S;
     static constexpr int V = 1 + DIM;
     static constexpr int NZ = 4;
     static constexpr int NL = CPB * DIM * NZ * F;
-    static constexpr int NLP = Fp64Pitch<n, DIM, NZ, CPB, Sh::TPB>::value;
-    static constexpr size_t picard = (size_t)n * NLP * 8;
+    static constexpr int NLP = MX ? Fp32Pitch<n, DIM, NZ, CPB, Sh::TPB>::value
+                                  : Fp64Pitch<n, DIM, NZ, CPB, Sh::TPB>::value;
+    static constexpr size_t picard = (size_t)n * NLP * sizeof(XT);
     static constexpr size_t faces = (size_t)2 * CPB * DIM * 2 * V * F * 8;  // q- and f-face adjoints
     // per-cell material-derivative terms, summed in a fixed order: one per face
     // node side (Rusanov speed) and one per thread (the rest)
@@ -106,15 +163,40 @@ struct AdjLayout {
     __device__ static int half_line(int L) { return (L / (2 * F)) * (NZ * F) + L % (2 * F); }
 };
 
-template <int DIM, int N>
+// Input of a mixed-precision contraction: x rounded to FP32, then to format P.
+// The empty asm keeps the two roundings apart: here the compiler would
+// otherwise fold them into one FP64 -> FP16 rounding, a long integer sequence
+// (there is no such instruction) that also rounds differently at FP32
+// halfway points.
+template <int P>
+__device__ __forceinline__ float rnd_in(double x) {
+    float f = (float)x;
+    asm volatile("" : "+v"(f));
+    return widen(round_to<P>(f));
+}
+template <>
+__device__ __forceinline__ float rnd_in<P32>(double x) {
+    return (float)x;
+}
+__device__ __forceinline__ float rnd_in(double x, int fmt) {
+    return fmt == PF16 ? rnd_in<PF16>(x) : (fmt == PBF16 ? rnd_in<PBF16>(x) : rnd_in<P32>(x));
+}
+
+constexpr int kAdjScaleExp = 8;  // scaled largest incoming adjoint value in [2^7, 2^8)
+
+// PP: the predictor's contraction format (P64: the FP64 kernel); the volume
+// format of the mixed kernel is a.pv.
+template <int DIM, int N, int PP>
 __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_adjoint(AdjKArgs a) {
+    constexpr bool MX = PP != P64;
     using Sh = Shape<DIM, N>;
-    using AL = AdjLayout<DIM, N>;
+    using AL = AdjLayout<DIM, N, MX>;
+    using XT = typename AL::XT;
     using Pde = Acoustic<DIM>;
     constexpr int n = Sh::n, S = Sh::S, F = Sh::F, CPB = Sh::CPB, TPB = Sh::TPB, V = 1 + DIM;
     constexpr int NLP = AL::NLP;
     __shared__ __attribute__((aligned(16))) char smem[AL::bytes];
-    double *X = reinterpret_cast<double *>(smem);                                // [n][NLP]
+    XT *X = reinterpret_cast<XT *>(smem);                                    // [n][NLP]
     double *fbuf = reinterpret_cast<double *>(smem + AL::bytes - AL::red);  // [NRI] Rusanov-speed terms
     double *kbuf = fbuf + AL::NRI;                                           // [TPB] per-thread terms
 
@@ -144,6 +226,11 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
     }
     constexpr int NHALF = CPB * DIM * 2 * F;  // slot 0/1 lines
 
+    // largest |incoming adjoint| of each cell (bit patterns of non-negative
+    // doubles order like the values), for the mixed kernel's input scale
+    __shared__ unsigned long long cmax[CPB];
+    if constexpr (MX)
+        if (tid < CPB) cmax[tid] = 0ull;
     double Qn[V], lam[V];
 #pragma unroll
     for (int v = 0; v < V; v++) {
@@ -165,6 +252,15 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
             zd[t][v] = 0.0;
         }
     auto src_term = [&](int b) { return a.src_s[b] * src_phi; };
+    // inputs of the predictor's and the volume's contractions
+    auto in_p = [&](double x) -> XT {
+        if constexpr (MX) return rnd_in<PP>(x);
+        else return x;
+    };
+    auto in_v = [&](double x) -> XT {
+        if constexpr (MX) return rnd_in(x, a.pv);
+        else return x;
+    };
 #pragma unroll 1
     for (int it = 0; it < iters; it++) {
 #pragma unroll
@@ -174,26 +270,31 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
 #pragma unroll
                 for (int j = 0; j < DIM; j++) {
                     const double vj = z[b][1 + j], p = z[b][0], vdj = zd[b][1 + j], pd = zd[b][0];
-                    X[po[j] + 0 * F] = active ? K * vj : 0.0;
-                    X[po[j] + 1 * F] = active ? p * irho : 0.0;
-                    X[po[j] + 2 * F] = active ? K * vdj + vj : 0.0;  // d(K v_j)/dK
-                    X[po[j] + 3 * F] = active ? pd * irho : 0.0;
+                    X[po[j] + 0 * F] = in_p(active ? K * vj : 0.0);
+                    X[po[j] + 1 * F] = in_p(active ? p * irho : 0.0);
+                    X[po[j] + 2 * F] = in_p(active ? K * vdj + vj : 0.0);  // d(K v_j)/dK
+                    X[po[j] + 3 * F] = in_p(active ? pd * irho : 0.0);
                 }
             }
             __syncthreads();
-            lines_inplace<n, false>(X, AL::NL, NLP, B->D, [](int L) { return L; }, tid, TPB);
+            if constexpr (MX)
+                lines_inplace<n, false>(X, AL::NL, NLP, B->Dp[PP], [](int L) { return L; }, tid, TPB);
+            else
+                lines_inplace<n, false>(X, AL::NL, NLP, B->D, [](int L) { return L; }, tid, TPB);
             __syncthreads();
             if (active) {
+                // the sum over directions belongs to the contraction's accumulation
                 double r[V], rd[V];
-                r[0] = 0.0;
-                rd[0] = 0.0;
+                XT r0 = 0, rd0 = 0;
 #pragma unroll
                 for (int j = 0; j < DIM; j++) {
-                    r[0] += X[po[j]];
-                    rd[0] += X[po[j] + 2 * F];
+                    r0 += X[po[j]];
+                    rd0 += X[po[j] + 2 * F];
                     r[1 + j] = X[po[j] + F];
                     rd[1 + j] = X[po[j] + 3 * F];
                 }
+                r[0] = r0;
+                rd[0] = rd0;
                 if (it == 0) {
 #pragma unroll
                     for (int t = 0; t < n; t++) {
@@ -259,8 +360,8 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
     __syncthreads();
 
     // ---- adjoint of the face integral and the Rusanov flux, per face node ----
-    double *gq = X;                                   // [cb][j][side][V][F]: adjoint of projected q
-    double *gf = X + (size_t)CPB * DIM * 2 * V * F;   // adjoint of projected F_j . e_j
+    double *gq = reinterpret_cast<double *>(smem);    // [cb][j][side][V][F]: adjoint of projected q
+    double *gf = gq + (size_t)CPB * DIM * 2 * V * F;  // adjoint of projected F_j . e_j
     {
         constexpr int NRI = AL::NRI;
         for (int itm = tid; itm < NRI; itm += TPB) {
@@ -278,12 +379,13 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
             const double sl = a.pde.mat[cl], sr = a.pde.mat[cr];
             const double sp = sl >= sr ? sl : sr;
             const bool c_is_max = side ? (sl >= sr) : (sr > sl);
-            double sbar = 0.0;
+            double sbar = 0.0, gmax = 0.0;
 #pragma unroll
             for (int v = 0; v < V; v++) {
                 const double lR = a.lamface[(((cr * DIM + j) * 2 + 0) * V + v) * (long)F + f];
                 const double lL = a.lamface[(((cl * DIM + j) * 2 + 1) * V + v) * (long)F + f];
                 const double G = a.sigma * (lR - lL);
+                gmax = fmax(gmax, fabs(G));
                 const double qm = a.fwdface[((((cl * DIM + j) * 2 + 1) * 2 + 0) * V + v) * (long)F + f];
                 const double qp = a.fwdface[((((cr * DIM + j) * 2 + 0) * 2 + 0) * V + v) * (long)F + f];
                 sbar += -0.5 * G * (qp - qm);
@@ -292,9 +394,28 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
                 gf[o] = 0.5 * G;
             }
             if (c_is_max) fbuf[itm] = sbar / (2.0 * rho * a.pde.mat[c]);
+            if constexpr (MX) atomicMax(&cmax[cbi], (unsigned long long)__double_as_longlong(gmax));
         }
+        if constexpr (MX)
+            if (active) {
+                double m = 0.0;
+#pragma unroll
+                for (int v = 0; v < V; v++) m = fmax(m, fabs(lam[v]));
+                atomicMax(&cmax[cb], (unsigned long long)__double_as_longlong(m));
+            }
     }
     __syncthreads();
+    // the cell's input scale sc and its inverse isc (1 in FP64)
+    double sc = 1.0, isc = 1.0;
+    if constexpr (MX) {
+        const double m = slot ? __longlong_as_double((long long)cmax[cb]) : 0.0;
+        if (m > 0.0) {
+            int e;
+            frexp(m, &e);
+            sc = ldexp(1.0, kAdjScaleExp - e);
+            isc = ldexp(1.0, e - kAdjScaleExp);
+        }
+    }
     // expand the face adjoints into the cell (transpose of the projection); of
     // the flux adjoints only the components of F_j that are not identically
     // zero (0 and 1+j) are needed
@@ -325,19 +446,22 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
     if (slot) {
 #pragma unroll
         for (int j = 0; j < DIM; j++) {
-            X[po[j]] = active ? lam[0] : 0.0;
-            X[po[j] + F] = active ? lam[1 + j] : 0.0;
+            X[po[j]] = in_v(active ? sc * lam[0] : 0.0);
+            X[po[j] + F] = in_v(active ? sc * lam[1 + j] : 0.0);
         }
     }
     __syncthreads();
-    lines_inplace<n, true>(X, NHALF, NLP, B->Kxi, [](int L) { return AL::half_line(L); }, tid, TPB);
+    if constexpr (MX)
+        lines_inplace<n, true>(X, NHALF, NLP, B->Kxip[a.pv], [](int L) { return AL::half_line(L); }, tid, TPB);
+    else
+        lines_inplace<n, true>(X, NHALF, NLP, B->Kxi, [](int L) { return AL::half_line(L); }, tid, TPB);
     __syncthreads();
     double kpart = 0.0;
     if (active) {
 #pragma unroll
         for (int j = 0; j < DIM; j++) {
-            fb0[j] += a.sigma * X[po[j]];
-            fbj[j] += a.sigma * X[po[j] + F];
+            fb0[j] += a.sigma * (isc * (double)X[po[j]]);
+            fbj[j] += a.sigma * (isc * (double)X[po[j] + F]);
         }
         // fbar_j = A_j qbar: qbar_adj += A_j^T fbar_adj, and dK through A_j
 #pragma unroll
@@ -353,16 +477,25 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
     // ---- transposed Picard iterations ----
     // rh[t]: adjoint of the iterate at time node t.  Each iteration first maps
     // the rows to Rbar_b = -dt sum_a Atau[a][b] rh_a, then slice b's row is
-    // replaced by (1/h) sum_j D_j^T A_j^T Rbar_b once its lines are done.  First
-    // iteration: rh_a = w_a qbb, so Rbar_b = wA[b] (-dt qbb) and one line pass
-    // serves every slice.
+    // replaced by (1/h) sum_j A_j^T D_j^T Rbar_b once its lines are done (D_j^T
+    // on components 0 and 1+j, the only ones A_j^T reads).  First iteration:
+    // rh_a = w_a qbb, so Rbar_b = wA[b] (-dt qbb) and, in FP64, one line pass
+    // serves every slice; the mixed kernel runs every slice, as the rounding of
+    // the inputs does not commute with the scaling by wA[b].
+    constexpr bool one_pass = !MX;
     double mu[V], rh[n][V];
 #pragma unroll
     for (int v = 0; v < V; v++) mu[v] = lam[v] + qbb[v];
+    if constexpr (!one_pass) {
+#pragma unroll
+        for (int t = 0; t < n; t++)
+#pragma unroll
+            for (int v = 0; v < V; v++) rh[t][v] = B->w[t] * qbb[v];
+    }
     __syncthreads();
 #pragma unroll 1
     for (int it = 0; it < iters; it++) {
-        if (it > 0 && active) {
+        if ((it > 0 || !one_pass) && active) {
 #pragma unroll
             for (int v = 0; v < V; v++) {
                 double tmp[n];
@@ -379,31 +512,35 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
         }
 #pragma unroll
         for (int b = 0; b < n; b++) {
-            if (it == 0 && b > 0) continue;
+            if (one_pass && it == 0 && b > 0) continue;
             double Rb[V];
 #pragma unroll
-            for (int v = 0; v < V; v++) Rb[v] = it == 0 ? -a.dt * qbb[v] : rh[b][v];
+            for (int v = 0; v < V; v++) Rb[v] = (one_pass && it == 0) ? -a.dt * qbb[v] : rh[b][v];
             if (slot) {
 #pragma unroll
                 for (int j = 0; j < DIM; j++) {
-                    X[po[j]] = active ? Rb[1 + j] * irho : 0.0;
-                    X[po[j] + F] = active ? K * Rb[0] : 0.0;
+                    X[po[j]] = in_p(active ? sc * Rb[0] : 0.0);
+                    X[po[j] + F] = in_p(active ? sc * Rb[1 + j] : 0.0);
                 }
             }
             __syncthreads();
-            lines_inplace<n, true>(X, NHALF, NLP, B->D, [](int L) { return AL::half_line(L); }, tid, TPB);
+            if constexpr (MX)
+                lines_inplace<n, true>(X, NHALF, NLP, B->Dp[PP], [](int L) { return AL::half_line(L); }, tid, TPB);
+            else
+                lines_inplace<n, true>(X, NHALF, NLP, B->D, [](int L) { return AL::half_line(L); }, tid, TPB);
             __syncthreads();
             if (active) {
+                // A_j^T (D_j^T Rbar)_j: component 0 from (1+j)/rho, 1+j from K * component 0
                 double nb_[V];
                 nb_[0] = 0.0;
 #pragma unroll
                 for (int j = 0; j < DIM; j++) {
-                    nb_[0] += X[po[j]];
-                    nb_[1 + j] = X[po[j] + F];
+                    nb_[0] += irho * (isc * (double)X[po[j] + F]);
+                    nb_[1 + j] = K * (isc * (double)X[po[j]]);
                 }
 #pragma unroll
                 for (int v = 0; v < V; v++) nb_[v] *= a.inv_h;
-                if (it == 0) {
+                if (one_pass && it == 0) {
 #pragma unroll
                     for (int bb = 0; bb < n; bb++)
 #pragma unroll

@@ -585,12 +585,15 @@ static aderdg_status step_adjoint(aderdg_solver *s, double dt, double t, const d
     if (!(dt > 0)) FAIL(s, ADERDG_E_INVALID, "dt must be positive");
     if (s->cfg.pde != ADERDG_ACOUSTIC || !s->dMat)
         FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint is built for acoustics with a per-cell material");
-    if (s->prec[ADERDG_K_PREDICTOR] || s->prec[ADERDG_K_VOLUME] || s->prec[ADERDG_K_FLUX])
-        FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint is FP64 only");
+    if (s->prec[ADERDG_K_FLUX]) FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint needs the flux kernel in FP64");
+    if ((s->prec[ADERDG_K_PREDICTOR] == ADERDG_FP64) != (s->prec[ADERDG_K_VOLUME] == ADERDG_FP64))
+        FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint needs the predictor and volume kernels both in FP64 or both lower");
     if (s->predictor != ADERDG_PICARD) FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint differentiates the Picard predictor");
     if (s->prec[ADERDG_K_STORAGE] != ADERDG_FP64) FAIL(s, ADERDG_E_UNSUPPORTED, "the adjoint needs the state in FP64");
     AdjointArgs a{};
-    a.pred = s->ks->pred[0];
+    a.pred = s->ks->pred[s->prec[ADERDG_K_PREDICTOR]];
+    a.prec_pred = s->prec[ADERDG_K_PREDICTOR];
+    a.prec_vol = s->prec[ADERDG_K_VOLUME];
     a.cfg_pde = s->cfg.pde;
     a.dim = s->d;
     a.order = s->cfg.order;

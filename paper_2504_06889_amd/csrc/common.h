@@ -30,7 +30,7 @@ struct Shape {
 };
 
 // ---------------------------------------------------------------------------
-// Basis constants (built on the host in FP64; see basis.cpp)
+// Basis constants (built on the host in FP64 by basis.hip)
 // ---------------------------------------------------------------------------
 struct DevBasis {
     double xi[kMaxN], w[kMaxN];

@@ -1,0 +1,147 @@
+"""Mixed-precision GPU adjoint (predictor and volume contractions in FP32, BF16
+or FP16, flux FP64) against the CPU oracle: the FP64 adjoint within the
+format's level, and the oracle's emulation of the same rounding points."""
+import numpy as np
+import pytest
+
+from oracle import misfit as omisfit
+from paper_2504_06889_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+UNIT = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -8, "fp16": 2.0 ** -11}
+
+
+def _setup(oracle_mod, dim, order, cells, prec, L=1.0, seed=0, source=True):
+    import torch
+    from paper_2504_06889_amd.aderdg import Solver
+    h = L / max(cells)
+    hi = tuple(c * h for c in cells)
+    args = (dim, order, cells, (0.0,) * dim, hi, "acoustic", (1.0, 2.25))
+    o = oracle_mod.Oracle(*args)
+    e = oracle_mod.Oracle(*args, prec=(prec[0], prec[1], "fp64"))
+    g = Solver(*args)
+    g.set_precisions(prec[0], prec[1], "fp64")
+    c = inputs.lognormal_speed(o.ncell, mean=1.5, sigma=0.2, seed=seed)
+    xs = [0.5 * L + 0.1 * h, 0.5 * hi[1] - 0.2 * h] + ([0.5 * hi[2] + 0.05 * h] if dim == 3 else [])
+    for s in (o, e, g):
+        s.set_material(c)
+        if source:
+            s.set_source(xs, 5.0, 0.2, 1.0)
+    dt = 0.5 * h / (dim * (2 * order + 1) * c.max())
+    return o, e, g, c, xs, dt, torch
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+SHAPES = [(3, 5, (2, 3, 2)), (3, 2, (3, 4, 2)), (2, 3, (5, 4))]
+PAIRS = [("fp32", "fp32"), ("bf16", "bf16"), ("fp16", "fp16"), ("fp16", "fp32")]
+
+
+@pytest.mark.parametrize("dim,order,cells", SHAPES)
+@pytest.mark.parametrize("pp,pv", PAIRS)
+def test_mixed_adjoint_step_matches_oracle(oracle_mod, dim, order, cells, pp, pv):
+    o, e, g, c, xs, dt, torch = _setup(oracle_mod, dim, order, cells, (pp, pv), seed=dim + order)
+    print("case", dim, order, cells, pp, pv, flush=True)
+    rng = np.random.default_rng(order)
+    Qn = rng.standard_normal(o.shape)
+    lam = rng.standard_normal(o.shape)
+    t = 0.13
+    mu64, g64 = o.adjoint_step(Qn, t, dt, lam, np.zeros(o.ncell))
+    mue, ge = e.adjoint_step(Qn, t, dt, lam, np.zeros(o.ncell))
+    ld = torch.from_numpy(lam).cuda()
+    gd = torch.zeros(o.ncell, dtype=torch.float64, device="cuda")
+    g.step_adjoint(dt, t, torch.from_numpy(Qn).cuda(), ld, gd)
+    mug, gg = ld.cpu().numpy(), gd.cpu().numpy()
+    assert np.all(np.isfinite(mug)) and np.all(np.isfinite(gg))
+    u = max(UNIT[pp], UNIT[pv])
+    r_mu, r_mu_emu, r_mu_ge = _rel(mug, mu64), _rel(mue, mu64), _rel(mug, mue)
+    r_g, r_g_emu = _rel(gg, g64), _rel(ge, g64)
+    print("levels mu gpu-vs-fp64 %.3e emu-vs-fp64 %.3e gpu-vs-emu %.3e | grad gpu-vs-fp64 %.3e emu-vs-fp64 %.3e"
+          % (r_mu, r_mu_emu, r_mu_ge, r_g, r_g_emu))
+    # within the format's level of the exact adjoint
+    assert r_mu < 0.5 * u and r_g < 2.0 * u, (r_mu, r_g, u)
+    assert r_mu < 10 * r_mu_emu + 1e-13 and r_g < 10 * r_g_emu + 1e-13
+    # the GPU rounds where the emulation rounds: closer to it than to FP64
+    if pp != "fp32":
+        assert r_mu_ge < 0.5 * r_mu_emu, (r_mu_ge, r_mu_emu)
+
+
+def test_mixed_adjoint_with_stored_faces_is_identical(oracle_mod):
+    """Face data copied after a mixed forward step give the same adjoint, bit for
+    bit, as their recomputation from the state with the same predictor."""
+    o, e, g, c, xs, dt, torch = _setup(oracle_mod, 3, 5, (3, 2, 4), ("fp16", "fp16"), seed=3)
+    rng = np.random.default_rng(5)
+    Qn = torch.from_numpy(rng.standard_normal(o.shape)).cuda()
+    lam = rng.standard_normal(o.shape)
+    t = 0.07
+    g.set_state(Qn)
+    g.time = t
+    g.step(dt, 1)
+    faces = g.copy_faces(torch.empty(g.face_bytes(), dtype=torch.uint8, device="cuda"))
+    l1, l2 = torch.from_numpy(lam).cuda(), torch.from_numpy(lam).cuda()
+    g1 = torch.zeros(o.ncell, dtype=torch.float64, device="cuda")
+    g2 = torch.zeros(o.ncell, dtype=torch.float64, device="cuda")
+    g.step_adjoint(dt, t, Qn, l1, g1)
+    g.step_adjoint(dt, t, Qn, l2, g2, fwd_faces=faces)
+    assert torch.equal(l1, l2) and torch.equal(g1, g2)
+
+
+@pytest.mark.parametrize("prec", [("fp16", "fp64", "fp64"), ("fp64", "fp16", "fp64"), ("fp16", "fp16", "fp16")])
+def test_mixed_adjoint_refuses_other_settings(prec):
+    import torch
+    from paper_2504_06889_amd.aderdg import AderdgError, Solver
+    g = Solver(3, 5, (2, 2, 2), (0.0,) * 3, (1.0,) * 3, "acoustic", (1.0, 2.25))
+    g.set_material(torch.ones(8, dtype=torch.float64, device="cuda"))
+    g.set_precisions(*prec)
+    z = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(AderdgError) as ei:
+        g.step_adjoint(1e-3, 0.0, z, z.clone(), torch.zeros(8, dtype=torch.float64, device="cuda"))
+    assert ei.value.code == -2
+
+
+@pytest.mark.parametrize("p", ["fp16", "bf16"])
+def test_mixed_misfit_gradient_matches_emulation(oracle_mod, p):
+    """Receiver misfit over 30 steps with the forward and the adjoint in the
+    format: the gradient against the FP64 one is at the level the oracle's
+    emulation of both predicts, and closer to the emulation than to FP64."""
+    from paper_2504_06889_amd import adjoint as adj
+    o, e, g, c, xs, dt, torch = _setup(oracle_mod, 3, 2, (4, 4, 4), (p, p), L=2.0, seed=5)
+    rec = inputs.receivers_near(xs, o.h, nrec=8, half_cells=1.5, seed=1)
+    g.set_receivers(rec)
+    nsteps = 30
+    Q0 = np.zeros(o.shape)
+    Q0d = torch.from_numpy(Q0).cuda()
+    data = omisfit.forward(o, Q0, np.full(o.ncell, 1.5), dt, nsteps, rec)[1]
+    cd = torch.from_numpy(c).cuda().requires_grad_(True)
+    J = adj.misfit(cd, g, Q0d, dt, nsteps, torch.from_numpy(data).cuda(), 7)
+    J.backward()
+    grad = cd.grad.cpu().numpy()
+    J64, g64, _ = omisfit.gradient(o, Q0, c, dt, nsteps, rec, data)
+    Je, ge, _ = omisfit.gradient(e, Q0, c, dt, nsteps, rec, data)
+    r, r_emu, r_ge = _rel(grad, g64), _rel(ge, g64), _rel(grad, ge)
+    print("misfit %s J %.6e J64 %.6e | grad gpu-vs-fp64 %.3e emu-vs-fp64 %.3e gpu-vs-emu %.3e"
+          % (p, float(J), J64, r, r_emu, r_ge))
+    assert abs(float(J) - J64) <= 10 * abs(Je - J64) + 1e-12 * J64
+    assert r < 10 * r_emu and r < 0.2
+    assert r_ge < r_emu
+
+
+@pytest.mark.parametrize("k", [-40, 30])
+def test_mixed_adjoint_scale_invariant(oracle_mod, k):
+    """2^k lam gives 2^k (mu, grad) bit for bit, as for the exact adjoint: the
+    per-cell input scale makes the rounded inputs independent of k, also far
+    below FP16's normal range."""
+    o, e, g, c, xs, dt, torch = _setup(oracle_mod, 3, 5, (2, 3, 2), ("fp16", "fp16"), seed=2)
+    rng = np.random.default_rng(4)
+    Qn = torch.from_numpy(rng.standard_normal(o.shape)).cuda()
+    lam = torch.from_numpy(rng.standard_normal(o.shape)).cuda()
+    s = 2.0 ** k
+    l1, l2 = lam.clone(), lam * s
+    g1 = torch.zeros(o.ncell, dtype=torch.float64, device="cuda")
+    g2 = torch.zeros(o.ncell, dtype=torch.float64, device="cuda")
+    g.step_adjoint(dt, 0.1, Qn, l1, g1)
+    g.step_adjoint(dt, 0.1, Qn, l2, g2)
+    assert torch.equal(l2, l1 * s) and torch.equal(g2, g1 * s)

@@ -166,3 +166,27 @@ def test_mixed_adjoint_refuses_other_settings(oracle_mod, prec):
     e.set_material(np.ones(e.ncell))
     with pytest.raises(ValueError):
         e.adjoint_step(np.zeros(e.shape), 0.0, 1e-3, np.zeros(e.shape), np.zeros(e.ncell))
+
+
+@pytest.mark.parametrize("pp,pv", [("fp16", "fp16"), ("bf16", "bf16"), ("fp16", "fp32")])
+@pytest.mark.parametrize("k", [-40, -7, 30])
+def test_mixed_adjoint_scale_invariant(oracle_mod, pp, pv, k):
+    """The exact adjoint is linear in lam, so 2^k lam gives 2^k (mu, grad) bit
+    for bit in FP64.  The mixed adjoint keeps that property through its
+    per-cell power-of-two input scale: the rounded inputs are the same for
+    every k, also where 2^k lam lies far below FP16's normal range (k = -40:
+    values near 1e-12) and would otherwise underflow."""
+    dim, order, cells = 3, 2, (3, 3, 2)
+    h = 1.0 / max(cells)
+    e = oracle_mod.Oracle(dim, order, cells, (0.0,) * dim, tuple(c * h for c in cells), "acoustic",
+                          (1.0, 2.25), prec=(pp, pv, "fp64"))
+    c = inputs.lognormal_speed(e.ncell, seed=4)
+    e.set_material(c)
+    dt = 0.3 * e.h / (dim * (2 * order + 1) * c.max())
+    rng = np.random.default_rng(9)
+    v = rng.standard_normal(e.shape)
+    w = rng.standard_normal(e.shape)
+    mu, g = e.adjoint_step(v, 0.0, dt, w, np.zeros(e.ncell))
+    s = 2.0 ** k
+    mus, gs = e.adjoint_step(v, 0.0, dt, s * w, np.zeros(e.ncell))
+    assert np.array_equal(mus, s * mu) and np.array_equal(gs, s * g)
