@@ -377,6 +377,10 @@ def main():
                     help="only run the per-kernel precision sweep on the Euler and shallow-water workloads")
     ap.add_argument("--paper-suite", action="store_true",
                     help="only run the paper's 2-D scenarios (27^2 cells, order 5) with lower-format kernels")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only run the adjoint configuration (forward and adjoint sweeps, FP64 and lower formats)")
+    ap.add_argument("--adjoint-steps", type=int, default=0,
+                    help="steps of the adjoint configuration (0: its own 200); with --adjoint-only")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (3 times), to scale HBM counters")
     args = ap.parse_args()
@@ -400,6 +404,15 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
         return
     torch.cuda.set_device(0)
+    if args.adjoint_only:
+        steps = args.adjoint_steps or None
+        txt = json.dumps({"adjoint": adjoint_bench(steps=steps, checkpoint=min(steps, 20) if steps else None,
+                                                   fd=steps is None)})
+        print(txt, flush=True)
+        if args.out:
+            with open(args.out, "w") as f:
+                f.write(txt + "\n")
+        return
     if args.sweep or args.paper_suite:
         txt = json.dumps({"sweep": sweep()} if args.sweep else {"paper_suite": paper_suite()})
         print(txt, flush=True)

@@ -81,16 +81,20 @@ __global__ __launch_bounds__(256) void k_lamface(const double *lam, double *out,
 }
 
 // In-place position-major line pass over the lines line_of(L), L < nl:
-// X[i][line] <- sum_k M(i,k) X[k][line] with M(i,k) = T ? Mat[k][i] : Mat[i][k],
-// accumulated in the element type of X (FP64, or FP32 on format-rounded inputs).
-template <int n, bool T, class XT, class MT, class LineOf>
+// X[i][line] <- sum_k M(i,k) rnd(X[k][line]) with M(i,k) = T ? Mat[k][i] : Mat[i][k],
+// accumulated in the element type of X (FP64, or FP32 with rnd rounding the
+// FP32 inputs to the contraction's format).
+struct NoRound {
+    __device__ double operator()(double x) const { return x; }
+};
+template <int n, bool T, class XT, class MT, class LineOf, class Rnd = NoRound>
 __device__ __forceinline__ void lines_inplace(XT *X, int nl, int NLP, MT Mat, LineOf line_of, int tid,
-                                              int nthreads) {
+                                              int nthreads, Rnd rnd = Rnd()) {
     for (int L = tid; L < nl; L += nthreads) {
         const int Ln = line_of(L);
         XT x[n];
 #pragma unroll
-        for (int k = 0; k < n; k++) x[k] = X[k * NLP + Ln];
+        for (int k = 0; k < n; k++) x[k] = rnd(X[k * NLP + Ln]);
 #pragma unroll
         for (int i = 0; i < n; i++) {
             XT y = 0;
@@ -163,24 +167,19 @@ struct AdjLayout {
     __device__ static int half_line(int L) { return (L / (2 * F)) * (NZ * F) + L % (2 * F); }
 };
 
-// Input of a mixed-precision contraction: x rounded to FP32, then to format P.
-// The empty asm keeps the two roundings apart: here the compiler would
-// otherwise fold them into one FP64 -> FP16 rounding, a long integer sequence
-// (there is no such instruction) that also rounds differently at FP32
-// halfway points.
+// Inputs of a mixed-precision contraction are rounded to FP32 as they are
+// written to the line buffer and to the format as the line pass reads them
+// (both from FP32: a rounding straight from FP64 to FP16 has no instruction).
 template <int P>
-__device__ __forceinline__ float rnd_in(double x) {
-    float f = (float)x;
-    asm volatile("" : "+v"(f));
-    return widen(round_to<P>(f));
-}
-template <>
-__device__ __forceinline__ float rnd_in<P32>(double x) {
-    return (float)x;
-}
-__device__ __forceinline__ float rnd_in(double x, int fmt) {
-    return fmt == PF16 ? rnd_in<PF16>(x) : (fmt == PBF16 ? rnd_in<PBF16>(x) : rnd_in<P32>(x));
-}
+struct RoundTo {
+    __device__ float operator()(float f) const { return widen(round_to<P>(f)); }
+};
+struct RoundToFmt {  // format chosen at run time (uniform)
+    int fmt;
+    __device__ float operator()(float f) const {
+        return fmt == PF16 ? widen(round_to<PF16>(f)) : (fmt == PBF16 ? widen(round_to<PBF16>(f)) : f);
+    }
+};
 
 constexpr int kAdjScaleExp = 8;  // scaled largest incoming adjoint value in [2^7, 2^8)
 
@@ -253,14 +252,9 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
         }
     auto src_term = [&](int b) { return a.src_s[b] * src_phi; };
     // inputs of the predictor's and the volume's contractions
-    auto in_p = [&](double x) -> XT {
-        if constexpr (MX) return rnd_in<PP>(x);
-        else return x;
-    };
-    auto in_v = [&](double x) -> XT {
-        if constexpr (MX) return rnd_in(x, a.pv);
-        else return x;
-    };
+    // inputs of the contractions, stored in the line buffer's type
+    auto in_p = [&](double x) -> XT { return (XT)x; };
+    auto in_v = in_p;
 #pragma unroll 1
     for (int it = 0; it < iters; it++) {
 #pragma unroll
@@ -278,7 +272,8 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
             }
             __syncthreads();
             if constexpr (MX)
-                lines_inplace<n, false>(X, AL::NL, NLP, B->Dp[PP], [](int L) { return L; }, tid, TPB);
+                lines_inplace<n, false>(X, AL::NL, NLP, B->Dp[PP], [](int L) { return L; }, tid, TPB,
+                                        RoundTo<PP>());
             else
                 lines_inplace<n, false>(X, AL::NL, NLP, B->D, [](int L) { return L; }, tid, TPB);
             __syncthreads();
@@ -452,7 +447,8 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
     }
     __syncthreads();
     if constexpr (MX)
-        lines_inplace<n, true>(X, NHALF, NLP, B->Kxip[a.pv], [](int L) { return AL::half_line(L); }, tid, TPB);
+        lines_inplace<n, true>(X, NHALF, NLP, B->Kxip[a.pv], [](int L) { return AL::half_line(L); }, tid, TPB,
+                               RoundToFmt{a.pv});
     else
         lines_inplace<n, true>(X, NHALF, NLP, B->Kxi, [](int L) { return AL::half_line(L); }, tid, TPB);
     __syncthreads();
@@ -525,7 +521,8 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
             }
             __syncthreads();
             if constexpr (MX)
-                lines_inplace<n, true>(X, NHALF, NLP, B->Dp[PP], [](int L) { return AL::half_line(L); }, tid, TPB);
+                lines_inplace<n, true>(X, NHALF, NLP, B->Dp[PP], [](int L) { return AL::half_line(L); }, tid, TPB,
+                                       RoundTo<PP>());
             else
                 lines_inplace<n, true>(X, NHALF, NLP, B->D, [](int L) { return AL::half_line(L); }, tid, TPB);
             __syncthreads();
