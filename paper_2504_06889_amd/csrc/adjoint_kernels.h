@@ -1,5 +1,5 @@
 // Discrete adjoint of the ADER-DG step for linear acoustics with a per-cell
-// sound speed c (bulk modulus K = rho c^2), FP64, gfx950.
+// sound speed c (bulk modulus K = rho c^2), FP64 or mixed precision, gfx950.
 //
 // The step is affine in Q for a fixed material, so the adjoint of Q is the
 // transpose of the step's linear part: face integral -> Rusanov flux -> face
@@ -16,7 +16,8 @@
 // -1/2 <G_adj, q+ - q-> ds/dK_c on each face where c is the larger speed
 // (ties go to the left cell).
 //
-// Mixed precision (k_adjoint<.., true>): the line buffer holds FP32 and each
+// Mixed precision (k_adjoint<.., PP> with PP the predictor's format, not
+// P64): the line buffer holds FP32 and each
 // transposed contraction runs in the format of the forward contraction it
 // transposes -- the derivative passes of the recomputed and of the transposed
 // Picard iterations in the predictor's format, the transposed volume operator
@@ -156,13 +157,22 @@ struct AdjLayout {
     static constexpr int NL = CPB * DIM * NZ * F;
     static constexpr int NLP = MX ? Fp32Pitch<n, DIM, NZ, CPB, Sh::TPB>::value
                                   : Fp64Pitch<n, DIM, NZ, CPB, Sh::TPB>::value;
-    static constexpr size_t picard = (size_t)n * NLP * sizeof(XT);
+    static constexpr size_t picard1 = (size_t)n * NLP * sizeof(XT);  // line buffer of one slice
     static constexpr size_t faces = (size_t)2 * CPB * DIM * 2 * V * F * 8;  // q- and f-face adjoints
     // per-cell material-derivative terms, summed in a fixed order: one per face
     // node side (Rusanov speed) and one per thread (the rest)
     static constexpr int NRI = CPB * DIM * 2 * F;
     static constexpr size_t red = (size_t)(NRI + Sh::TPB) * 8;
-    static constexpr size_t bytes = (picard > faces ? picard : faces) + red;
+    static constexpr size_t bytes_for(int spi) {
+        return (spi * picard1 > faces ? spi * picard1 : faces) + red;
+    }
+    // time slices per line pass: two where one cell fills the workgroup and
+    // three workgroups still fit in a CU's LDS -- half the barriers, twice the
+    // independent work between them (three slices measured slower: more
+    // registers live across the pass)
+    static constexpr int SPI = (CPB == 1 && 3 * bytes_for(2) <= 160 * 1024) ? 2 : 1;
+    static constexpr size_t bytes = bytes_for(SPI);
+    static constexpr int SLICE = n * NLP;  // element offset between the slices' buffers
     // line of the L-th slot-0/1 line (L < CPB*DIM*2*F)
     __device__ static int half_line(int L) { return (L / (2 * F)) * (NZ * F) + L % (2 * F); }
 };
@@ -230,12 +240,9 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
     __shared__ unsigned long long cmax[CPB];
     if constexpr (MX)
         if (tid < CPB) cmax[tid] = 0ull;
-    double Qn[V], lam[V];
+    double Qn[V];
 #pragma unroll
-    for (int v = 0; v < V; v++) {
-        Qn[v] = active ? a.Qn[(cell * V + v) * S + s] : 0.0;
-        lam[v] = active ? a.lam[(cell * V + v) * S + s] : 0.0;
-    }
+    for (int v = 0; v < V; v++) Qn[v] = active ? a.Qn[(cell * V + v) * S + s] : 0.0;
 
     // ---- forward Picard with its K-tangent ----
     // z[t] (zd[t]): the iterate (its K-derivative) at time node t; during an
@@ -251,74 +258,94 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
             zd[t][v] = 0.0;
         }
     auto src_term = [&](int b) { return a.src_s[b] * src_phi; };
-    // inputs of the predictor's and the volume's contractions
     // inputs of the contractions, stored in the line buffer's type
     auto in_p = [&](double x) -> XT { return (XT)x; };
     auto in_v = in_p;
-#pragma unroll 1
-    for (int it = 0; it < iters; it++) {
+    // slices b0 .. b0+SPI-1 share a line pass, slice b0+q in the q-th buffer
+    constexpr int SPI = AL::SPI, SLICE = AL::SLICE;
+    // (two forms of the same map: the FP64 kernel spills less with the first,
+    // the mixed one runs faster with the second)
+    auto full_line = [](int L) {
+        if constexpr (!MX) return L % AL::NL + (L / AL::NL) * SLICE;
+        else return L < AL::NL ? L : L - AL::NL + SLICE;
+    };
+    // One line pass over the slices b0 .. b0+nsl-1.  first: the first
+    // iteration, whose slices all equal (Q, 0): one slice, then every row
+    // q_t = Q - sigma (Arow[t] h R_0 - h source terms), tangent likewise.
+    auto fwd_group = [&](int b0, int nsl, bool first) __attribute__((always_inline)) {
+        if (slot) {
 #pragma unroll
-        for (int b = 0; b < n; b++) {
-            if (it == 0 && b > 0) continue;
-            if (slot) {
+            for (int q = 0; q < SPI; q++) {
+                const int b = b0 + q;
+                if (b >= n || q >= nsl) continue;
 #pragma unroll
                 for (int j = 0; j < DIM; j++) {
                     const double vj = z[b][1 + j], p = z[b][0], vdj = zd[b][1 + j], pd = zd[b][0];
-                    X[po[j] + 0 * F] = in_p(active ? K * vj : 0.0);
-                    X[po[j] + 1 * F] = in_p(active ? p * irho : 0.0);
-                    X[po[j] + 2 * F] = in_p(active ? K * vdj + vj : 0.0);  // d(K v_j)/dK
-                    X[po[j] + 3 * F] = in_p(active ? pd * irho : 0.0);
-                }
-            }
-            __syncthreads();
-            if constexpr (MX)
-                lines_inplace<n, false>(X, AL::NL, NLP, B->Dp[PP], [](int L) { return L; }, tid, TPB,
-                                        RoundTo<PP>());
-            else
-                lines_inplace<n, false>(X, AL::NL, NLP, B->D, [](int L) { return L; }, tid, TPB);
-            __syncthreads();
-            if (active) {
-                // the sum over directions belongs to the contraction's accumulation
-                double r[V], rd[V];
-                XT r0 = 0, rd0 = 0;
-#pragma unroll
-                for (int j = 0; j < DIM; j++) {
-                    r0 += X[po[j]];
-                    rd0 += X[po[j] + 2 * F];
-                    r[1 + j] = X[po[j] + F];
-                    rd[1 + j] = X[po[j] + 3 * F];
-                }
-                r[0] = r0;
-                rd[0] = rd0;
-                if (it == 0) {
-#pragma unroll
-                    for (int t = 0; t < n; t++) {
-#pragma unroll
-                        for (int v = 0; v < V; v++) {
-                            double acc = B->Arow[t] * r[v];
-                            if (v == 0 && src_here) {
-#pragma unroll
-                                for (int bb = 0; bb < n; bb++) acc = fma(B->Atau[t][bb], -src_term(bb), acc);
-                            }
-                            z[t][v] = fma(-a.sigma, acc, Qn[v]);
-                            zd[t][v] = -a.sigma * (B->Arow[t] * rd[v]);
-                        }
-                    }
-                } else {
-                    if (src_here) r[0] -= src_term(b);
-#pragma unroll
-                    for (int t = 0; t < n; t++)
-                        if (t == b) {
-#pragma unroll
-                            for (int v = 0; v < V; v++) {
-                                z[t][v] = r[v];
-                                zd[t][v] = rd[v];
-                            }
-                        }
+                    XT *x = X + q * SLICE + po[j];
+                    x[0 * F] = in_p(active ? K * vj : 0.0);
+                    x[1 * F] = in_p(active ? p * irho : 0.0);
+                    x[2 * F] = in_p(active ? K * vdj + vj : 0.0);  // d(K v_j)/dK
+                    x[3 * F] = in_p(active ? pd * irho : 0.0);
                 }
             }
         }
-        if (it > 0 && active) {
+        __syncthreads();
+        if constexpr (MX)
+            lines_inplace<n, false>(X, nsl * AL::NL, NLP, B->Dp[PP], full_line, tid, TPB, RoundTo<PP>());
+        else
+            lines_inplace<n, false>(X, nsl * AL::NL, NLP, B->D, full_line, tid, TPB);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < SPI; q++) {
+            const int b = b0 + q;
+            if (b >= n || q >= nsl || !active) continue;
+            // the sum over directions belongs to the contraction's accumulation
+            double r[V], rd[V];
+            XT r0 = 0, rd0 = 0;
+#pragma unroll
+            for (int j = 0; j < DIM; j++) {
+                const XT *x = X + q * SLICE + po[j];
+                r0 += x[0];
+                rd0 += x[2 * F];
+                r[1 + j] = x[F];
+                rd[1 + j] = x[3 * F];
+            }
+            r[0] = r0;
+            rd[0] = rd0;
+            if (first) {
+#pragma unroll
+                for (int t = 0; t < n; t++) {
+#pragma unroll
+                    for (int v = 0; v < V; v++) {
+                        double acc = B->Arow[t] * r[v];
+                        if (v == 0 && src_here) {
+#pragma unroll
+                            for (int bb = 0; bb < n; bb++) acc = fma(B->Atau[t][bb], -src_term(bb), acc);
+                        }
+                        z[t][v] = fma(-a.sigma, acc, Qn[v]);
+                        zd[t][v] = -a.sigma * (B->Arow[t] * rd[v]);
+                    }
+                }
+            } else {
+                if (src_here) r[0] -= src_term(b);
+#pragma unroll
+                for (int t = 0; t < n; t++)
+                    if (t == b) {
+#pragma unroll
+                        for (int v = 0; v < V; v++) {
+                            z[t][v] = r[v];
+                            zd[t][v] = rd[v];
+                        }
+                    }
+            }
+        }
+    };
+    fwd_group(0, 1, true);
+#pragma unroll 1
+    for (int it = 1; it < iters; it++) {
+#pragma unroll
+        for (int b0 = 0; b0 < n; b0 += SPI) fwd_group(b0, b0 + SPI <= n ? SPI : n - b0, false);
+        if (active) {
 #pragma unroll
             for (int v = 0; v < V; v++) {
                 double r[n], rd[n];
@@ -353,6 +380,10 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
         }
     }
     __syncthreads();
+    // the incoming adjoint of this cell (read here, not earlier: registers)
+    double lam[V];
+#pragma unroll
+    for (int v = 0; v < V; v++) lam[v] = active ? a.lam[(cell * V + v) * S + s] : 0.0;
 
     // ---- adjoint of the face integral and the Rusanov flux, per face node ----
     double *gq = reinterpret_cast<double *>(smem);    // [cb][j][side][V][F]: adjoint of projected q
@@ -489,74 +520,97 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
             for (int v = 0; v < V; v++) rh[t][v] = B->w[t] * qbb[v];
     }
     __syncthreads();
+    // the rows to Rbar_b = -dt sum_a Atau[a][b] rh_a
+    auto adj_map = [&]() __attribute__((always_inline)) {
+        if (!active) return;
+#pragma unroll
+        for (int v = 0; v < V; v++) {
+            double tmp[n];
+#pragma unroll
+            for (int t = 0; t < n; t++) tmp[t] = rh[t][v];
+#pragma unroll
+            for (int b = 0; b < n; b++) {
+                double r = 0.0;
+#pragma unroll
+                for (int t = 0; t < n; t++) r = fma(B->Atau[t][b], tmp[t], r);
+                rh[b][v] = -a.dt * r;
+            }
+        }
+    };
+    // One line pass over the slices b0 .. b0+nsl-1; first: the FP64 kernel's
+    // single pass of the first iteration.
+    auto pair_line = [](int L) {
+        if constexpr (!MX) return AL::half_line(L % NHALF) + (L / NHALF) * SLICE;
+        else return L < NHALF ? AL::half_line(L) : AL::half_line(L - NHALF) + SLICE;
+    };
+    auto adj_group = [&](int b0, int nsl, bool first) __attribute__((always_inline)) {
+        if (slot) {
+#pragma unroll
+            for (int q = 0; q < SPI; q++) {
+                const int b = b0 + q;
+                if (b >= n || q >= nsl) continue;
+                double Rb[V];
+#pragma unroll
+                for (int v = 0; v < V; v++) Rb[v] = first ? -a.dt * qbb[v] : rh[b][v];
+#pragma unroll
+                for (int j = 0; j < DIM; j++) {
+                    XT *x = X + q * SLICE + po[j];
+                    x[0] = in_p(active ? sc * Rb[0] : 0.0);
+                    x[F] = in_p(active ? sc * Rb[1 + j] : 0.0);
+                }
+            }
+        }
+        __syncthreads();
+        if constexpr (MX)
+            lines_inplace<n, true>(X, nsl * NHALF, NLP, B->Dp[PP], pair_line, tid, TPB, RoundTo<PP>());
+        else
+            lines_inplace<n, true>(X, nsl * NHALF, NLP, B->D, pair_line, tid, TPB);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < SPI; q++) {
+            const int b = b0 + q;
+            if (b >= n || q >= nsl || !active) continue;
+            // A_j^T (D_j^T Rbar)_j: component 0 from (1+j)/rho, 1+j from K * component 0
+            double nb_[V];
+            nb_[0] = 0.0;
+#pragma unroll
+            for (int j = 0; j < DIM; j++) {
+                const XT *x = X + q * SLICE + po[j];
+                nb_[0] += irho * (isc * (double)x[F]);
+                nb_[1 + j] = K * (isc * (double)x[0]);
+            }
+#pragma unroll
+            for (int v = 0; v < V; v++) nb_[v] *= a.inv_h;
+            if (first) {
+#pragma unroll
+                for (int bb = 0; bb < n; bb++)
+#pragma unroll
+                    for (int v = 0; v < V; v++) {
+                        rh[bb][v] = B->wA[bb] * nb_[v];
+                        mu[v] += rh[bb][v];
+                    }
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; v++) mu[v] += nb_[v];
+#pragma unroll
+                for (int t = 0; t < n; t++)
+                    if (t == b) {
+#pragma unroll
+                        for (int v = 0; v < V; v++) rh[t][v] = nb_[v];
+                    }
+            }
+        }
+    };
+    int it0 = 0;
+    if constexpr (one_pass) {
+        adj_group(0, 1, true);
+        it0 = 1;
+    }
 #pragma unroll 1
-    for (int it = 0; it < iters; it++) {
-        if ((it > 0 || !one_pass) && active) {
+    for (int it = it0; it < iters; it++) {
+        adj_map();
 #pragma unroll
-            for (int v = 0; v < V; v++) {
-                double tmp[n];
-#pragma unroll
-                for (int t = 0; t < n; t++) tmp[t] = rh[t][v];
-#pragma unroll
-                for (int b = 0; b < n; b++) {
-                    double r = 0.0;
-#pragma unroll
-                    for (int t = 0; t < n; t++) r = fma(B->Atau[t][b], tmp[t], r);
-                    rh[b][v] = -a.dt * r;
-                }
-            }
-        }
-#pragma unroll
-        for (int b = 0; b < n; b++) {
-            if (one_pass && it == 0 && b > 0) continue;
-            double Rb[V];
-#pragma unroll
-            for (int v = 0; v < V; v++) Rb[v] = (one_pass && it == 0) ? -a.dt * qbb[v] : rh[b][v];
-            if (slot) {
-#pragma unroll
-                for (int j = 0; j < DIM; j++) {
-                    X[po[j]] = in_p(active ? sc * Rb[0] : 0.0);
-                    X[po[j] + F] = in_p(active ? sc * Rb[1 + j] : 0.0);
-                }
-            }
-            __syncthreads();
-            if constexpr (MX)
-                lines_inplace<n, true>(X, NHALF, NLP, B->Dp[PP], [](int L) { return AL::half_line(L); }, tid, TPB,
-                                       RoundTo<PP>());
-            else
-                lines_inplace<n, true>(X, NHALF, NLP, B->D, [](int L) { return AL::half_line(L); }, tid, TPB);
-            __syncthreads();
-            if (active) {
-                // A_j^T (D_j^T Rbar)_j: component 0 from (1+j)/rho, 1+j from K * component 0
-                double nb_[V];
-                nb_[0] = 0.0;
-#pragma unroll
-                for (int j = 0; j < DIM; j++) {
-                    nb_[0] += irho * (isc * (double)X[po[j] + F]);
-                    nb_[1 + j] = K * (isc * (double)X[po[j]]);
-                }
-#pragma unroll
-                for (int v = 0; v < V; v++) nb_[v] *= a.inv_h;
-                if (one_pass && it == 0) {
-#pragma unroll
-                    for (int bb = 0; bb < n; bb++)
-#pragma unroll
-                        for (int v = 0; v < V; v++) {
-                            rh[bb][v] = B->wA[bb] * nb_[v];
-                            mu[v] += rh[bb][v];
-                        }
-                } else {
-#pragma unroll
-                    for (int v = 0; v < V; v++) mu[v] += nb_[v];
-#pragma unroll
-                    for (int t = 0; t < n; t++)
-                        if (t == b) {
-#pragma unroll
-                            for (int v = 0; v < V; v++) rh[t][v] = nb_[v];
-                        }
-                }
-            }
-        }
+        for (int b0 = 0; b0 < n; b0 += SPI) adj_group(b0, b0 + SPI <= n ? SPI : n - b0, false);
     }
 
     if (active) {
