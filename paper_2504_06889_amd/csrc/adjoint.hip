@@ -41,10 +41,9 @@ using AdjFn = void (*)(const AdjKArgs &, hipStream_t);
 template <int DIM, int N, int PP = P64>
 struct AdjInstance {
     static void lamface(const double *lam, double *out, long ncell, const DevBasis *B, hipStream_t st) {
-        const long total = ncell * DIM * 2 * (1 + DIM) * Shape<DIM, N>::F;
-        long g = (total + 255) / 256;
-        if (g > 65536) g = 65536;
-        hipLaunchKernelGGL((k_lamface<DIM, N>), dim3(g), dim3(256), 0, st, lam, out, ncell, B);
+        constexpr int LCB = LamFaceShape<DIM, N>::LCB;
+        hipLaunchKernelGGL((k_lamface<DIM, N>), dim3((ncell + LCB - 1) / LCB), dim3(256), 0, st, lam, out, ncell,
+                           B);
     }
     static void adjoint(const AdjKArgs &a, hipStream_t st) {
         using Sh = Shape<DIM, N>;

@@ -55,29 +55,44 @@ struct AdjKArgs {
     int pv;                // volume contraction format (Prec) of the mixed kernel
 };
 
-// lamface[c][j][side][v][f] = sum_i L_side[i] lam[c][v][node(f, j, i)]
+// lamface[c][j][side][v][f] = sum_i L_side[i] lam[c][v][node(f, j, i)].  A
+// workgroup stages the incoming adjoint of LCB cells in LDS with coalesced
+// loads and writes their face restrictions, contiguous per cell, coalesced.
+template <int DIM, int N>
+struct LamFaceShape {
+    static constexpr int n = N + 1, S = ipow(n, DIM), F = ipow(n, DIM - 1), V = 1 + DIM;
+    static constexpr int VS = V * S, OUT = DIM * 2 * V * F;  // values in, restrictions out per cell
+    static constexpr int LCB = VS >= 1024 ? 1 : 1024 / VS;   // cells per workgroup
+};
+
 template <int DIM, int N>
 __global__ __launch_bounds__(256) void k_lamface(const double *lam, double *out, long ncell,
                                                  const DevBasis *B) {
-    using Sh = Shape<DIM, N>;
-    constexpr int n = Sh::n, S = Sh::S, F = Sh::F, V = 1 + DIM;
-    const long total = ncell * DIM * 2 * V * F;
-    for (long i = blockIdx.x * 256L + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
-        const int f = i % F;
-        long r = i / F;
+    using LS = LamFaceShape<DIM, N>;
+    constexpr int n = LS::n, S = LS::S, F = LS::F, V = LS::V, VS = LS::VS, OUT = LS::OUT, LCB = LS::LCB;
+    __shared__ double sl[LCB * VS];
+    const long c0 = (long)blockIdx.x * LCB;
+    const int nc = ncell - c0 < LCB ? (int)(ncell - c0) : LCB;
+    const double *src = lam + c0 * VS;
+    for (int i = threadIdx.x; i < nc * VS; i += 256) sl[i] = src[i];
+    __syncthreads();
+    double *dst = out + c0 * OUT;
+    for (int o = threadIdx.x; o < nc * OUT; o += 256) {
+        const int cb = o / OUT;
+        int r = o % OUT;
+        const int f = r % F;
+        r /= F;
         const int v = r % V;
         r /= V;
         const int side = r % 2;
-        r /= 2;
-        const int j = r % DIM;
-        const long c = r / DIM;
+        const int j = r / 2;
         const int st = j == 0 ? 1 : (j == 1 ? n : n * n);
-        const double *src = lam + (c * V + v) * S + line_start<n>(f, j);
+        const double *line = sl + cb * VS + v * S + line_start<n>(f, j);
         const double *L = side ? B->L1 : B->L0;
         double y = 0.0;
 #pragma unroll
-        for (int k = 0; k < n; k++) y = fma(L[k], src[k * st], y);
-        out[i] = y;
+        for (int k = 0; k < n; k++) y = fma(L[k], line[k * st], y);
+        dst[o] = y;
     }
 }
 
