@@ -8,7 +8,9 @@ Q, plus the material derivative) swept backwards, with the receiver residuals
 injected at each step.  States are checkpointed every `checkpoint` steps in
 the forward run and each segment is recomputed once in the backward sweep; the
 recomputation also keeps each step's forward face data, which the adjoint step
-needs, instead of having it recomputed from the stored state.
+needs, instead of having it recomputed from the stored state.  With the
+solver's predictor and volume kernels set to a lower format, the forward steps
+and the adjoint steps both run their contractions in it.
 """
 import torch
 
