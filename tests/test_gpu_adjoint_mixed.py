@@ -145,3 +145,42 @@ def test_mixed_adjoint_scale_invariant(oracle_mod, k):
     g.step_adjoint(dt, 0.1, Qn, l1, g1)
     g.step_adjoint(dt, 0.1, Qn, l2, g2)
     assert torch.equal(l2, l1 * s) and torch.equal(g2, g1 * s)
+
+
+def test_mixed_adjoint_fullsize_properties():
+    """The adjoint configuration's grid (64^3 cells, N=5) in the launch shape the
+    benchmark times: the FP16 adjoint step is within the format's level of the
+    FP64 one (half a unit roundoff for the adjoint, two for the gradient: the
+    bounds the oracle's emulation meets on small grids) and invariant, bit for
+    bit, under lam -> 2^-30 lam."""
+    import torch
+    from paper_2504_06889_amd.aderdg import Solver
+    sc = inputs.SCENARIOS["adjoint_acoustic3d_n5_64"]
+    ex = sc.extra
+    g = Solver.from_scenario(sc)
+    print("case adjoint_acoustic3d_n5_64 fp16 vs fp64", flush=True)
+    c = torch.from_numpy(inputs.lognormal_speed(g.ncell, ex["c_mean"], ex["c_sigma"], ex["seed_c"])).cuda()
+    g.set_material(c)
+    dt = g.max_dt(sc.cfl)
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    Qn = torch.randn(g.shape, dtype=torch.float64, device="cuda", generator=gen)
+    lam = torch.randn(g.shape, dtype=torch.float64, device="cuda", generator=gen)
+
+    def adjoint(l):
+        lo = l.clone()
+        go = torch.zeros(g.ncell, dtype=torch.float64, device="cuda")
+        g.step_adjoint(dt, 0.0, Qn, lo, go)
+        return lo, go
+    mu64, g64 = adjoint(lam)
+    g.set_precisions("fp16", "fp16", "fp64")
+    mu16, g16 = adjoint(lam)
+    s = 2.0 ** -30
+    mus, gs = adjoint(lam * s)
+    g.set_precisions("fp64", "fp64", "fp64")
+    u = UNIT["fp16"]
+    rm = float((mu16 - mu64).norm() / mu64.norm())
+    rg = float((g16 - g64).norm() / g64.norm())
+    print("fullsize mu %.3e grad %.3e (u %.3e)" % (rm, rg, u))
+    assert 1e-3 * u < rm < 0.5 * u and 1e-3 * u < rg < 2.0 * u, (rm, rg)
+    assert torch.equal(mus, mu16 * s) and torch.equal(gs, g16 * s)
+    g.close()
