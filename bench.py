@@ -385,7 +385,7 @@ def main():
                     help="only run a plain device copy of this many MiB (3 times), to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the step is not sharded across GPUs in this build "
+        print("bench.py runs on one GPU only: the step is not sharded across GPUs "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
