@@ -12,6 +12,9 @@ route than ``aderdg_oracle.c``:
   sum_k (-dt A d/dx)^k / (k+1)! Q.
 * ``fv_rusanov_step``: the textbook first-order Rusanov finite-volume update,
   which is what the scheme reduces to at N = 0.
+* ``fv_swe_step``: the first-order path-conservative finite-volume update of
+  the shallow-water system with the well-balanced Rusanov-type flux (eq.
+  swe_custom_riemann), what the scheme reduces to at N = 0 for shallow water.
 """
 import math
 
@@ -37,6 +40,17 @@ def lagrange_polys(nodes):
 
 def _val(c, x):
     return npleg.legval(2.0 * x - 1.0, c)
+
+
+def nodal_basis_at(n, loc):
+    """Tensor-product Lagrange basis on n Gauss-Legendre nodes per dimension at
+    the reference point loc in [0,1]^d: phi[S] with node s = i0 + n i1 + ..."""
+    xi, _ = gl_nodes01(n)
+    ps = lagrange_polys(xi)
+    out = np.ones(1)
+    for x in loc:
+        out = np.multiply.outer(np.array([_val(p, x) for p in ps]), out).reshape(-1)
+    return out
 
 
 def _der(c):
@@ -70,15 +84,18 @@ def _kron_all(mats):
     return out
 
 
-def dense_predictor(Q, A_list, n, h, dt):
+def dense_predictor(Q, A_list, n, h, dt, source=None):
     """Exact solution of the cell-local space-time system of eq. Picard for a
-    linear PDE q_t + sum_j A_j q_{x_j} = 0 with constant matrices A_j.
+    linear PDE q_t + sum_j A_j q_{x_j} = S with constant matrices A_j.
 
     Q: [V][S] nodal state (S = n^d, x fastest).  Returns q: [n][V][S], the
     space-time nodal values at the Gauss-Legendre time nodes.
 
     Weak form divided by h^d: (T1 (x) Ms) q + (dt/h) sum_j (Mt (x) Gj (x) M..) A_j q
-    = (F0 (x) Ms) Q, with all 1-D integrals exact."""
+    = (F0 (x) Ms) Q + dt (Mt (x) Ms) S, with all 1-D integrals exact.  `source`:
+    None, or (var, phi[S], s[n]) for a source s(t_a) phi in the equation of
+    variable `var`, given by its values at the space-time nodes (the point
+    source of eq. exa_canonical_form projected onto the nodal basis)."""
     d = len(A_list)
     V = Q.shape[0]
     M, G, T1, F0, _ = one_d_integrals(n)
@@ -94,6 +111,11 @@ def dense_predictor(Q, A_list, n, h, dt):
     for j, A in enumerate(A_list):
         lhs = lhs + (dt / h) * np.kron(M, np.kron(A, space_op(j, G)))
     rhs = np.kron(F0[:, None], np.kron(np.eye(V), Ms)) @ Q.reshape(-1)
+    if source is not None:
+        var, phi, svals = source
+        Sn = np.zeros((n, V, Q.shape[1]))
+        Sn[:, var, :] = np.outer(svals, phi)
+        rhs = rhs + dt * (np.kron(M, np.kron(np.eye(V), Ms)) @ Sn.reshape(-1))
     q = np.linalg.solve(lhs, rhs)
     return q.reshape(n, V, -1)
 
@@ -150,3 +172,41 @@ def step_matrix(oracle, dt, t=0.0):
         oracle.step(t, dt)
         M[:, i] = oracle.get_state().reshape(-1)
     return M
+
+
+def fv_swe_step(U, dt, h, g):
+    """One first-order finite-volume step of the shallow-water system, periodic.
+
+    U: [4, C_y, C_x] cell averages of (h, hu, hv, b).  Written from eq. swe_cons
+    (fluxes (hu_j, hu u_j, hv u_j, 0)), eq. swe_noncons (the term g h d(h + b)/dx_j
+    in the j-momentum) and eq. swe_custom_riemann: at every face between a left
+    state L and a right state R along x_j, the conservative flux is the centred
+    flux with a dissipation that acts on the surface eta = h + b and on the
+    discharges, scaled by the largest characteristic speed |u_j| + sqrt(g h) of
+    the two states; the non-conservative product along the straight path from L
+    to R, g * (h_L + h_R)/2 * (eta_R - eta_L), is split in halves between the
+    two cells.  With a piecewise-constant state the cell interiors contribute
+    nothing, so the update is
+        U_i <- U_i - dt/h [ (G + P/2)_{i+1/2} - (G - P/2)_{i-1/2} ]
+    with G the flux and P the path integral (in the j-momentum only)."""
+    out = U.copy()
+    for j in range(2):
+        ax = 2 - j                      # array axis of direction x_j (x fastest)
+        L, R = U, np.roll(U, -1, axis=ax)   # the face on the right of each cell
+
+        def flux(q):
+            uj = q[1 + j] / q[0]
+            return np.stack([q[1 + j], q[1] * uj, q[2] * uj, 0.0 * q[0]])
+
+        def speed(q):
+            return np.abs(q[1 + j] / q[0]) + np.sqrt(g * q[0])
+
+        s = np.maximum(speed(L), speed(R))
+        jump = np.stack([(R[0] + R[3]) - (L[0] + L[3]), R[1] - L[1], R[2] - L[2], 0.0 * L[0]])
+        G = 0.5 * (flux(L) + flux(R)) - 0.5 * s * jump
+        P = np.zeros_like(G)
+        P[1 + j] = g * 0.5 * (L[0] + R[0]) * ((R[0] + R[3]) - (L[0] + L[3]))
+        right = G + 0.5 * P                          # leaves cell i through its right face
+        left = np.roll(G - 0.5 * P, 1, axis=ax)      # enters cell i through its left face
+        out = out - dt / h * (right - left)
+    return out

@@ -8,7 +8,8 @@ oracle take their inputs from here.
 
 Scenarios (arXiv 2504.06889, Sec. 4):
   planar waves  Q = omega sin(omega t - k.x) q0 with (omega, q0) an eigenpair
-                of sum_j k_j A_j (Sec. 4.2.1), acoustic and elastic;
+                of sum_j k_j A_j (Sec. 5.2, planar waves), acoustic and elastic,
+                and 3-D elastic P and S plane waves along an oblique k;
   Euler         advected density sine wave (exact: shifted initial state), the
                 smooth Gaussian bell (Sec. 4.3.1, exp(-50 r^2) reading) and the
                 static isentropic vortex (Sec. 4.3.2, with p = (1+dT)^(g/(g-1))
@@ -101,6 +102,57 @@ def planar_elastic(coords, t, rho, lam, mu, kP, kS):
     return _pack([rP[v] * sP + rS[v] * sS for v in range(len(rP))], coords)
 
 
+def elastic_plane_waves(coords, t, rho, lam, mu, k, pols):
+    """Superposed plane waves of the 3-D elastic system along one wave vector k.
+
+    The system (the 3-D form of eq. equations_of_motion): d sigma_ij/dt =
+    lambda delta_ij div v + mu (d_i v_j + d_j v_i), rho dv_i/dt = sum_j
+    d_j sigma_ij.  For a velocity v = a d sin(omega t - k.x) with a unit
+    polarisation d, the momentum and stress equations hold when
+    rho omega^2 d = (lambda + mu) k (k.d) + mu |k|^2 d, i.e. d parallel to k
+    with omega = cp |k| (P wave) or d orthogonal to k with omega = cs |k|
+    (S wave), and the stress amplitude is
+        S_ij = -(lambda delta_ij (k.d) + mu (k_i d_j + k_j d_i)) / omega.
+    `pols` lists (amplitude, polarisation) pairs; each polarisation must be
+    parallel or orthogonal to k.  Variables (sxx, syy, szz, sxy, syz, sxz, vx,
+    vy, vz); k must be periodic on the domain."""
+    X = _grid(coords)
+    k = np.asarray(k, dtype=np.float64)
+    kn = float(np.linalg.norm(k))
+    cp = math.sqrt((lam + 2 * mu) / rho)
+    cs = math.sqrt(mu / rho)
+    phase_x = sum(k[j] * X[j] for j in range(3))
+    fields = [0.0 * phase_x for _ in range(9)]
+    pairs = ((0, 0, 0), (1, 1, 1), (2, 2, 2), (3, 0, 1), (4, 1, 2), (5, 0, 2))
+    for amp, d in pols:
+        d = np.asarray(d, dtype=np.float64)
+        d = d / np.linalg.norm(d)
+        kd = float(k @ d)
+        if abs(abs(kd) - kn) < 1e-12 * kn:
+            omega = cp * kn
+        elif abs(kd) < 1e-12 * kn:
+            omega = cs * kn
+        else:
+            raise ValueError("polarisation must be parallel or orthogonal to k")
+        s = amp * np.sin(omega * t - phase_x)
+        for v, i, j in pairs:
+            S = -((lam * kd if i == j else 0.0) + mu * (k[i] * d[j] + k[j] * d[i])) / omega
+            fields[v] = fields[v] + S * s
+        for i in range(3):
+            fields[6 + i] = fields[6 + i] + d[i] * s
+    return _pack(fields, coords)
+
+
+def planar_elastic_oblique(coords, t, rho, lam, mu, k=(2 * math.pi,) * 3, amp_p=1.0, amp_s=1.0):
+    """P wave and S wave along k (default 2 pi (1, 1, 1)), the S wave polarised
+    along (k_y, -k_x, 0): every stress and velocity component varies, and
+    sigma_yz and sigma_xz differ."""
+    k = np.asarray(k, dtype=np.float64)
+    dP = k / np.linalg.norm(k)
+    dS = np.array([k[1], -k[0], 0.0])
+    return elastic_plane_waves(coords, t, rho, lam, mu, k, [(amp_p, dP), (amp_s, dS)])
+
+
 # --------------------------------------------------------------------------
 # Euler (Sec. 4.3)
 # --------------------------------------------------------------------------
@@ -157,6 +209,28 @@ def swe_bump(coords, eta0=2.0, bump=0.1, width=200.0, pert=0.01):
     b = bump * np.exp(-width * ((X - 0.5) ** 2 + (Y - 0.5) ** 2))
     h = eta0 - b + pert * np.sin(2 * np.pi * (X + Y))
     return _pack([h, 0.0 * h, 0.0 * h, b + 0.0 * h], coords)
+
+
+def swe_gravity_wave(coords, t, g, depth=2.0, bottom=0.25, flow=(0.4, -0.25),
+                     k=(2 * math.pi, 4 * math.pi), eps=1e-7):
+    """Small gravity wave on a uniform stream over a flat bottom.
+
+    Linearising eq. swe about h = depth, v = flow, b = bottom (constant) gives
+    h'_t + flow.grad h' + depth div v' = 0 and v'_t + flow.grad v' + g grad h' = 0,
+    solved by h' = eps sin(k.x - omega t), v' = eps (c / depth) k/|k| sin(k.x - omega t)
+    with c = sqrt(g depth) and omega = k.flow + c |k|.  The state is
+    (depth + h', (depth + h') (flow + v'), bottom): the full nonlinear system
+    differs from it by O(eps^2)."""
+    X, Y = _grid(coords)
+    kx, ky = k
+    kn = math.hypot(kx, ky)
+    c = math.sqrt(g * depth)
+    omega = kx * flow[0] + ky * flow[1] + c * kn
+    s = eps * np.sin(kx * X + ky * Y - omega * t)
+    h = depth + s
+    u = flow[0] + (c / depth) * (kx / kn) * s
+    v = flow[1] + (c / depth) * (ky / kn) * s
+    return _pack([h, h * u, h * v, bottom + 0.0 * h], coords)
 
 
 def zeros(coords, nvars):
@@ -221,10 +295,10 @@ SCENARIOS = {
                                  (1.0, 1.0), (1.0, 1.0), 10, 0.7, "planar_acoustic",
                                  {"k": (2 * math.pi, 2 * math.pi)}),
     # 3-D elastic wave (9 vars), N = 5, 64^3 periodic cells, rho = 2.7, cp = 6, cs = 3.464,
-    # planar P + S wave, 100 steps.
+    # planar P + S wave along k = 2 pi (1, 1, 1) (S polarised along (1, -1, 0)), 100 steps.
     "elastic3d_n5_64": Scenario("elastic3d_n5_64", "elastic", 3, 5, (64, 64, 64), (0.0,) * 3,
                                 (1.0,) * 3, _elastic_params(2.7, 6.0, 3.464), 100, 0.5,
-                                "planar_elastic", {"kP": 2 * math.pi, "kS": 2 * math.pi}),
+                                "planar_elastic_oblique", {"k": (2 * math.pi,) * 3}),
     # 3-D compressible Euler, N = 4, 48^3 cells, density sine wave, 200 steps.
     "euler3d_n4_48": Scenario("euler3d_n4_48", "euler", 3, 4, (48, 48, 48), (0.0,) * 3,
                               (1.0,) * 3, (1.4,), 200, 0.6, "euler_density_wave"),
@@ -282,6 +356,17 @@ def evaluate(sc, coords, t=0.0):
     if sc.ic == "planar_elastic":
         rho, lam, mu = sc.params[:3]
         return planar_elastic(coords, t, rho, lam, mu, sc.extra["kP"], sc.extra["kS"])
+    if sc.ic == "planar_elastic_oblique":
+        rho, lam, mu = sc.params[:3]
+        ex = sc.extra
+        return planar_elastic_oblique(coords, t, rho, lam, mu, ex.get("k", (2 * math.pi,) * 3),
+                                      ex.get("amp_p", 1.0), ex.get("amp_s", 1.0))
+    if sc.ic == "elastic_plane_waves":
+        rho, lam, mu = sc.params[:3]
+        return elastic_plane_waves(coords, t, rho, lam, mu, sc.extra["k"], sc.extra["pols"])
+    if sc.ic == "swe_gravity_wave":
+        ex = {k_: v_ for k_, v_ in sc.extra.items() if k_ in ("depth", "bottom", "flow", "k", "eps")}
+        return swe_gravity_wave(coords, t, sc.params[0], **ex)
     if sc.ic == "euler_density_wave":
         return euler_density_wave(coords, t, sc.params[0])
     if sc.ic == "euler_bell":

@@ -69,6 +69,43 @@ def test_predictor_equals_dense_space_time_solve(oracle_mod, pde, dim, order, pa
         np.testing.assert_allclose(fbar[j], mats[j] @ qbar, atol=1e-11 * scale)
 
 
+@pytest.mark.parametrize("dim,order", [(2, 3), (3, 2)])
+def test_predictor_with_point_source_equals_dense_solve(oracle_mod, dim, order):
+    """A point source s(t) delta(x - xs) in the pressure equation (eq.
+    exa_canonical_form) enters the space-time system as dt (Mt x Ms) S with S
+    its nodal projection s(t_a) phi_k(xs) / (h^d W_k); the converged Picard
+    iterate equals the dense solve with that right-hand side.  The spatial
+    operator is nilpotent of index d N + 1; the source puts part of the initial
+    error outside its range, so d N + 1 iterations are exact."""
+    n = order + 1
+    K, rho = 2.25, 1.0
+    o = oracle_mod.Oracle(dim, order, [1] * dim, [0.0] * dim, [0.5] * dim, "acoustic", (rho, K),
+                          picard_iters=dim * order + 1)
+    rng = np.random.default_rng(21 + dim)
+    Q = rng.standard_normal(o.shape)
+    o.set_state(Q)
+    xs = 0.5 * rng.random(dim)
+    f0, t0, amp, t = 3.0, 0.4, 1.7, 0.25
+    o.set_source(xs, f0, t0, amp)
+    dt = 0.3 * o.h
+    qst, _, _, _ = o.predict_cell(0, t, dt)
+    xi, w = brute.gl_nodes01(n)
+    W = np.ones(1)
+    for _ in range(dim):
+        W = np.multiply.outer(w, W).reshape(-1)
+    phi = brute.nodal_basis_at(n, xs / o.h) / (o.h ** dim * W)
+
+    def ricker(tt):
+        a = (math.pi * f0 * (tt - t0)) ** 2
+        return amp * (1 - 2 * a) * math.exp(-a)
+    svals = np.array([ricker(t + x * dt) for x in xi])
+    ref = brute.dense_predictor(Q[0], _acoustic_mats(dim, K, rho), n, o.h, dt, source=(0, phi, svals))
+    ref0 = brute.dense_predictor(Q[0], _acoustic_mats(dim, K, rho), n, o.h, dt)
+    scale = np.abs(ref).max()
+    assert np.abs(ref - ref0).max() > 1e-3 * scale  # the source matters
+    assert np.abs(qst - ref).max() < 1e-12 * scale
+
+
 def test_default_picard_count_is_not_converged_in_2d(oracle_mod):
     """I = N+1 (the default reading) differs from the converged predictor in
     2-D for linear systems only by a small truncation, decreasing with I."""
