@@ -106,6 +106,37 @@ def _torch():
     return torch
 
 
+def check_tensor(x, name, numel, dtype="float64", device=None):
+    """Validate a tensor before its pointer goes to the library: dtype, contiguity
+    and element count first (these checks need no GPU), then that it lives on the
+    solver's device.  Raises ValueError; nothing is launched."""
+    return check_tensors([(x, name, numel, dtype)], device)[0]
+
+
+def check_tensors(items, device=None):
+    """check_tensor over (tensor, name, numel[, dtype]) items: the host-side
+    checks of every item before the device checks of any."""
+    torch = _torch()
+    for it in items:
+        x, name, numel = it[:3]
+        dtype = it[3] if len(it) > 3 else "float64"
+        if not isinstance(x, torch.Tensor):
+            raise ValueError("%s must be a torch tensor, got %s" % (name, type(x).__name__))
+        if x.dtype != getattr(torch, dtype):
+            raise ValueError("%s must be %s, got %s" % (name, dtype, x.dtype))
+        if not x.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        if x.numel() != numel:
+            raise ValueError("%s must hold %d elements, got %d" % (name, numel, x.numel()))
+    for it in items:
+        x, name = it[:2]
+        if not x.is_cuda:
+            raise ValueError("%s must be a device (CUDA/HIP) tensor" % name)
+        if device is not None and x.device.index != device:
+            raise ValueError("%s is on device %s, the solver on cuda:%d" % (name, x.device, device))
+    return [it[0] for it in items]
+
+
 class Solver:
     """One ADER-DG solver on the current HIP device and stream (see include/aderdg.h)."""
 
@@ -128,6 +159,7 @@ class Solver:
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
+        self.device = torch.cuda.current_device()
         handle = ctypes.c_void_p()
         rc = lib().aderdg_create(ctypes.byref(c), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(handle))
         if rc != 0:
@@ -168,11 +200,14 @@ class Solver:
     def shape(self):
         return (self.ncell, self.V, self.S)
 
+    def _state_numel(self):
+        return self.ncell * self.V * self.S
+
     # -- state ---------------------------------------------------------------
     def set_state(self, Q):
         torch = _torch()
         if isinstance(Q, torch.Tensor) and Q.is_cuda:
-            assert Q.dtype == torch.float64 and Q.is_contiguous() and tuple(Q.shape) == self.shape
+            check_tensor(Q, "Q", self._state_numel(), device=self.device)
             self._check(lib().aderdg_set_state(self._h, ctypes.c_void_p(Q.data_ptr()), 1))
         else:
             Qh = np.ascontiguousarray(Q, dtype=np.float64)
@@ -183,7 +218,7 @@ class Solver:
         """Copy the state out: into `out` (a CUDA float64 tensor) or a new numpy array."""
         torch = _torch()
         if out is not None and isinstance(out, torch.Tensor):
-            assert out.is_cuda and out.dtype == torch.float64 and tuple(out.shape) == self.shape
+            check_tensor(out, "out", self._state_numel(), device=self.device)
             self._check(lib().aderdg_get_state(self._h, ctypes.c_void_p(out.data_ptr()), 1))
             return out
         Qh = np.empty(self.shape)
@@ -193,10 +228,12 @@ class Solver:
     def set_material(self, c):
         torch = _torch()
         if isinstance(c, torch.Tensor) and c.is_cuda:
+            check_tensor(c, "c", self.ncell, device=self.device)
             self._check(lib().aderdg_set_material(self._h, ctypes.c_void_p(c.data_ptr()), 1))
         else:
             ch = np.ascontiguousarray(c, dtype=np.float64).reshape(-1)
-            assert ch.size == self.ncell
+            if ch.size != self.ncell:
+                raise ValueError("c must hold %d values, got %d" % (self.ncell, ch.size))
             self._check(lib().aderdg_set_material(self._h, ctypes.c_void_p(ch.ctypes.data), 0))
 
     def set_precision(self, kernel, prec):
@@ -258,9 +295,8 @@ class Solver:
                                                pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
     def read_receivers(self, out=None):
-        torch = _torch()
         if out is not None:
-            assert out.is_cuda and out.dtype == torch.float64 and out.numel() == self.nrec
+            check_tensor(out, "out", self.nrec, device=self.device)
             self._check(lib().aderdg_read_receivers(self._h, ctypes.c_void_p(out.data_ptr()), 1))
             return out
         r = np.zeros(self.nrec)
@@ -276,7 +312,10 @@ class Solver:
 
     def copy_faces(self, out):
         """Copy the last step's face data into `out` (a CUDA uint8 tensor of face_bytes())."""
-        assert out.is_cuda and out.is_contiguous() and out.numel() * out.element_size() >= self.face_bytes()
+        nb = self.face_bytes()
+        check_tensor(out, "out", out.numel(), dtype="uint8", device=self.device)
+        if out.numel() < nb:
+            raise ValueError("out must hold at least %d bytes, got %d" % (nb, out.numel()))
         self._check(lib().aderdg_copy_faces(self._h, ctypes.c_void_p(out.data_ptr()), 1))
         return out
 
@@ -284,19 +323,24 @@ class Solver:
         """lam <- (step Jacobian)^T lam, grad += d<lam, step(Qn)>/dc (device tensors).
         fwd_faces: the face data copied right after the forward step from Qn (else they
         are recomputed from Qn)."""
-        for x in (Qn, lam, grad):
-            assert x.is_cuda and x.is_contiguous()
+        check_tensors([(Qn, "Qn", self._state_numel()), (lam, "lam", self._state_numel()),
+                       (grad, "grad", self.ncell)], self.device)
         if fwd_faces is None:
             self._check(lib().aderdg_step_adjoint(self._h, float(dt), float(t), ctypes.c_void_p(Qn.data_ptr()),
                                                   ctypes.c_void_p(lam.data_ptr()),
                                                   ctypes.c_void_p(grad.data_ptr())))
         else:
-            assert fwd_faces.is_cuda and fwd_faces.is_contiguous()
+            check_tensor(fwd_faces, "fwd_faces", fwd_faces.numel(), dtype="uint8", device=self.device)
+            if fwd_faces.numel() < self.face_bytes():
+                raise ValueError("fwd_faces must hold at least %d bytes" % self.face_bytes())
             self._check(lib().aderdg_step_adjoint_faces(
                 self._h, float(dt), float(t), ctypes.c_void_p(Qn.data_ptr()), ctypes.c_void_p(fwd_faces.data_ptr()),
                 ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(grad.data_ptr())))
 
     def receivers_adjoint(self, weight, lam):
+        """lam[cell][0][node] += sum_r weight[r] phi_node(x_r) (device tensors)."""
+        check_tensors([(weight, "weight", getattr(self, "nrec", 0)), (lam, "lam", self._state_numel())],
+                      self.device)
         self._check(lib().aderdg_receivers_adjoint(self._h, ctypes.c_void_p(weight.data_ptr()),
                                                    ctypes.c_void_p(lam.data_ptr())))
 

@@ -26,8 +26,10 @@ class ReceiverMisfit(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, c, solver, Q0, dt, nsteps, data, checkpoint=20, t0=0.0):
-        assert isinstance(solver, Solver)
-        c = c.detach().contiguous()
+        if not isinstance(solver, Solver):
+            raise TypeError("solver must be an aderdg.Solver")
+        # the library takes FP64 per-cell values; a lower-precision c is widened here
+        c = c.detach().to(torch.float64).contiguous()
         solver.set_material(c)
         solver.set_state(Q0)
         solver.time = t0
