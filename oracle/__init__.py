@@ -43,7 +43,8 @@ class _Config(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("order", ctypes.c_int), ("cells", ctypes.c_int * 3),
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3), ("pde", ctypes.c_int),
                 ("params", ctypes.c_double * 8), ("picard_iters", ctypes.c_int),
-                ("prec", ctypes.c_int * 3), ("predictor", ctypes.c_int), ("storage", ctypes.c_int)]
+                ("prec", ctypes.c_int * 3), ("predictor", ctypes.c_int), ("storage", ctypes.c_int),
+                ("semantics", ctypes.c_int), ("prec_picard", ctypes.c_int)]
 
 PREDICTORS = {"picard": 0, "ck": 1}
 
@@ -83,6 +84,7 @@ def lib():
         L.or_cell_size.restype = ctypes.c_double
         L.or_cell_size.argtypes = [vp]
         L.or_num_threads.restype = ctypes.c_int
+        L.or_set_num_threads.argtypes = [ctypes.c_int]
         L.or_adjoint_step.argtypes = [vp, dp, ctypes.c_double, ctypes.c_double, dp, dp, dp]
         L.or_point_weights.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), dp]
         _lib = L
@@ -119,6 +121,11 @@ def num_threads():
     return lib().or_num_threads()
 
 
+def set_num_threads(n):
+    """Threads the oracle's loops use from now on."""
+    lib().or_set_num_threads(int(n))
+
+
 def nvars(pde, dim):
     return lib().or_nvars(PDE_IDS.get(pde, pde), dim)
 
@@ -127,7 +134,8 @@ class Oracle:
     """FP64 CPU ADER-DG on a periodic Cartesian grid (state layout [cell][var][node])."""
 
     def __init__(self, dim, order, cells, lo, hi, pde, params, picard_iters=0,
-                 prec=(FP64, FP64, FP64), predictor="picard", storage="fp64"):
+                 prec=(FP64, FP64, FP64), predictor="picard", storage="fp64", semantics="build",
+                 prec_picard=None):
         c = _Config()
         c.dim, c.order = dim, order
         cells = list(cells) + [1] * (3 - len(cells))
@@ -146,6 +154,12 @@ class Oracle:
         self.predictor = predictor
         c.storage = PREC_IDS.get(storage, storage)
         self.storage = storage
+        # "build": contraction inputs rounded, FP32 accumulation (the GPU path's
+        # semantics); "paper": each kernel computes and stores in its type
+        # (prec[0] predictor kernel, prec_picard its Picard loop, prec[2] corrector)
+        c.semantics = {"build": 0, "paper": 1}[semantics]
+        c.prec_picard = -1 if prec_picard is None else PREC_IDS.get(prec_picard, prec_picard)
+        self.semantics = semantics
         self._cfg = c
         self._h = lib().or_create(ctypes.byref(c))
         if not self._h:

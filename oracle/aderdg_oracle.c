@@ -399,6 +399,8 @@ or_solver *or_create(const or_config *cfg)
     int V = or_nvars(cfg->pde, cfg->dim);
     if (V <= 0 || V > MAXV) return NULL;
     if (cfg->storage < OR_FP64 || cfg->storage > OR_FP16) return NULL;
+    if (cfg->semantics == OR_SEM_PAPER && (cfg->predictor != OR_PICARD || cfg->prec_picard > OR_FP16))
+        return NULL; /* paper semantics: Picard predictor only */
     if (cfg->predictor != OR_PICARD &&
         (cfg->predictor != OR_CK || (cfg->pde != OR_ACOUSTIC && cfg->pde != OR_ELASTIC)))
         return NULL; /* the CK procedure needs a linear flux */
@@ -855,8 +857,11 @@ static void correct_cell(const or_solver *s, int64_t cell, double dt, const doub
 }
 
 /* One full time step t -> t + dt over every cell (Alg. 1). */
+static int step_paper(or_solver *s, double t, double dt);
+
 int or_step(or_solver *s, double t, double dt)
 {
+    if (s->c.semantics == OR_SEM_PAPER) return step_paper(s, t, dt);
     const size_t VS = (size_t)s->V * s->S;
     const size_t FS = (size_t)s->d * 2 * s->V * s->F;
     double *Qn = (double *)malloc(sizeof(double) * s->ncell * VS);
@@ -886,6 +891,317 @@ int or_step(or_solver *s, double t, double dt)
                 bf[1 + 2 * j + side] = ff + nc * FS;
             }
         correct_cell(s, c, dt, bq, bf, Qn + c * VS);
+        store_round(s, Qn + c * VS, VS);
+    }
+    free(fq);
+    free(ff);
+    free(s->Q);
+    s->Q = Qn;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Paper semantics (Sec. 4.1, Sec. 7): each kernel computes in its own type.  */
+/* Every arithmetic result inside a kernel is rounded to the kernel's type p  */
+/* (one rounding per operation, no fused multiply-add; constants and inputs   */
+/* converted to p first).  Written out separately from the FP64 step above so */
+/* that its rounding points can be read off line by line.                     */
+/* ------------------------------------------------------------------------ */
+
+static double rp(int p, double x) { return or_round(p, x); }
+static double add_p(int p, double a, double b) { return rp(p, a + b); }
+static double sub_p(int p, double a, double b) { return rp(p, a - b); }
+static double mul_p(int p, double a, double b) { return rp(p, a * b); }
+static double div_p(int p, double a, double b) { return rp(p, a / b); }
+
+/* Physical flux F_j(q) with every operation in type p (q already in p). */
+static void paper_flux(const or_solver *s, int64_t cell, const double *q, int j, int p, double *F)
+{
+    const int d = s->d;
+    const double *pr = s->c.params;
+    switch (s->c.pde) {
+    case OR_ACOUSTIC: {
+        double rho = rp(p, pr[0]), K = rp(p, cell_bulk(s, cell));
+        F[0] = mul_p(p, K, q[1 + j]);
+        for (int i = 0; i < d; i++) F[1 + i] = (i == j) ? div_p(p, q[0], rho) : 0.0;
+        break;
+    }
+    case OR_ELASTIC: {
+        double rho = rp(p, pr[0]), lam = rp(p, pr[1]), mu = rp(p, pr[2]);
+        double l2m = add_p(p, lam, mul_p(p, rp(p, 2.0), mu));
+        int ns = d * (d + 1) / 2;
+        const double *v = q + ns;
+        for (int a = 0; a < d; a++)
+            for (int b = a; b < d; b++) {
+                int k = stress_index(d, a, b);
+                if (a == b)
+                    F[k] = -mul_p(p, a == j ? l2m : lam, v[j]);
+                else
+                    F[k] = (b == j) ? -mul_p(p, mu, v[a]) : ((a == j) ? -mul_p(p, mu, v[b]) : 0.0);
+            }
+        for (int i = 0; i < d; i++) F[ns + i] = -div_p(p, q[stress_index(d, i, j)], rho);
+        break;
+    }
+    case OR_EULER: {
+        double g = rp(p, pr[0]), rho = q[0], E = q[1 + d];
+        double ke = 0.0;
+        for (int i = 0; i < d; i++) ke = add_p(p, ke, mul_p(p, q[1 + i], q[1 + i]));
+        double pres = mul_p(p, sub_p(p, g, 1.0), sub_p(p, E, div_p(p, mul_p(p, 0.5, ke), rho)));
+        double uj = div_p(p, q[1 + j], rho);
+        F[0] = q[1 + j];
+        for (int i = 0; i < d; i++) F[1 + i] = (i == j) ? add_p(p, mul_p(p, q[1 + i], uj), pres)
+                                                          : mul_p(p, q[1 + i], uj);
+        F[1 + d] = mul_p(p, uj, add_p(p, E, pres));
+        break;
+    }
+    case OR_SWE: {
+        double uj = div_p(p, q[1 + j], q[0]);
+        F[0] = q[1 + j];
+        F[1] = mul_p(p, q[1], uj);
+        F[2] = mul_p(p, q[2], uj);
+        F[3] = 0.0;
+        break;
+    }
+    }
+}
+
+static double paper_max_eig(const or_solver *s, int64_t cell, const double *q, int j, int p)
+{
+    const int d = s->d;
+    const double *pr = s->c.params;
+    switch (s->c.pde) {
+    case OR_ACOUSTIC: return rp(p, sqrt(div_p(p, rp(p, cell_bulk(s, cell)), rp(p, pr[0]))));
+    case OR_ELASTIC:
+        return rp(p, sqrt(div_p(p, add_p(p, rp(p, pr[1]), mul_p(p, 2.0, rp(p, pr[2]))), rp(p, pr[0]))));
+    case OR_EULER: {
+        double g = rp(p, pr[0]), rho = q[0], E = q[1 + d], ke = 0.0;
+        for (int i = 0; i < d; i++) ke = add_p(p, ke, mul_p(p, q[1 + i], q[1 + i]));
+        double pres = mul_p(p, sub_p(p, g, 1.0), sub_p(p, E, div_p(p, mul_p(p, 0.5, ke), rho)));
+        return add_p(p, fabs(div_p(p, q[1 + j], rho)), rp(p, sqrt(div_p(p, mul_p(p, g, pres), rho))));
+    }
+    case OR_SWE: return add_p(p, fabs(div_p(p, q[1 + j], q[0])), rp(p, sqrt(mul_p(p, rp(p, pr[0]), q[0]))));
+    }
+    return 0.0;
+}
+
+/* sum_k m[k] x[k*stride] in type p: m converted to p, each product and each
+ * partial sum rounded. */
+static double contract_p(int n, const double *m, const double *x, int stride, int p)
+{
+    double a = 0.0;
+    for (int k = 0; k < n; k++) a = add_p(p, a, mul_p(p, rp(p, m[k]), x[k * stride]));
+    return a;
+}
+
+static void apply_dir_p(const or_solver *s, const double *M, int j, const double *X, double *out, int nv, int p)
+{
+    const int n = s->n, S = s->S, st = stride_of(j, n);
+    for (int v = 0; v < nv; v++)
+        for (int sn = 0; sn < S; sn++) {
+            int i = coord(sn, j, n);
+            out[v * S + sn] = contract_p(n, M + i * n, X + v * S + (sn - i * st), st, p);
+        }
+}
+
+/* R(q_b) = (1/h) (sum_j D_j F_j(q_b) + non-conservative product), type p. */
+static void paper_residual(const or_solver *s, int64_t cell, const double *qb, int p, cell_work *w, double *R)
+{
+    const int S = s->S, V = s->V, d = s->d;
+    const double inv_h = rp(p, 1.0 / s->h);
+    for (int sn = 0; sn < S; sn++) {
+        double q[MAXV], F[MAXV];
+        for (int v = 0; v < V; v++) q[v] = qb[v * S + sn];
+        for (int j = 0; j < d; j++) {
+            paper_flux(s, cell, q, j, p, F);
+            for (int v = 0; v < V; v++) w->Fj[(j * V + v) * S + sn] = F[v];
+        }
+    }
+    for (int i = 0; i < V * S; i++) R[i] = 0.0;
+    for (int j = 0; j < d; j++) {
+        apply_dir_p(s, s->D, j, w->Fj + (size_t)j * V * S, w->tmp, V, p);
+        for (int i = 0; i < V * S; i++) R[i] = add_p(p, R[i], w->tmp[i]);
+    }
+    if (s->c.pde == OR_SWE) {
+        const double g = rp(p, s->c.params[0]);
+        for (int sn = 0; sn < S; sn++) w->eta[sn] = add_p(p, qb[0 * S + sn], qb[3 * S + sn]);
+        for (int j = 0; j < d; j++) {
+            apply_dir_p(s, s->D, j, w->eta, w->deta, 1, p);
+            for (int sn = 0; sn < S; sn++)
+                R[(1 + j) * S + sn] = add_p(p, R[(1 + j) * S + sn], mul_p(p, mul_p(p, g, qb[0 * S + sn]), w->deta[sn]));
+        }
+    }
+    for (int i = 0; i < V * S; i++) R[i] = mul_p(p, R[i], inv_h);
+}
+
+/* The predictor kernel of one cell in type pp (Picard loop in pq): reads the
+ * stored state Q, writes the face projections fq/ff [d][2][V][F] (type pp) and
+ * Q* = Q + sigma sum_j Kxi_j Fbar_j (- sigma Nbar) in type pp. */
+static void paper_predictor(const or_solver *s, int64_t cell, double dt, int pp, int pq, cell_work *w,
+                            double *Qstar, double *fq, double *ff)
+{
+    const int n = s->n, S = s->S, V = s->V, d = s->d, F = s->F;
+    const size_t VS = (size_t)V * S;
+    const double *Q = s->Q + cell * VS;
+    /* Picard iteration in pq */
+    double *Qq = w->tmp;  /* not used by paper_residual's first phase; copied below */
+    double *Q0 = (double *)malloc(sizeof(double) * VS);
+    for (size_t i = 0; i < VS; i++) Q0[i] = rp(pq, Q[i]);
+    (void)Qq;
+    const double dtq = rp(pq, dt);
+    for (int a = 0; a < n; a++) memcpy(w->q + a * VS, Q0, VS * sizeof(double));
+    for (int r = 0; r < s->I; r++) {
+        for (int b = 0; b < n; b++) paper_residual(s, cell, w->q + b * VS, pq, w, w->R + b * VS);
+        for (int a = 0; a < n; a++)
+            for (size_t i = 0; i < VS; i++) {
+                double acc = 0.0;
+                for (int b = 0; b < n; b++) acc = add_p(pq, acc, mul_p(pq, rp(pq, s->Atau[a * n + b]), w->R[b * VS + i]));
+                w->qn[a * VS + i] = sub_p(pq, Q0[i], mul_p(pq, dtq, acc));
+            }
+        double *t_ = w->q; w->q = w->qn; w->qn = t_;
+    }
+    /* the rest of the predictor kernel in pp: the iterate converted to pp */
+    for (size_t i = 0; i < (size_t)n * VS; i++) w->q[i] = rp(pp, w->q[i]);
+    double *qbar = (double *)calloc(VS, sizeof(double));
+    double *fbar = (double *)calloc((size_t)d * VS, sizeof(double));
+    double *nbar = (double *)calloc(VS, sizeof(double));
+    for (int a = 0; a < n; a++) {
+        const double wa = rp(pp, s->w[a]);
+        const double *qa = w->q + a * VS;
+        for (size_t i = 0; i < VS; i++) qbar[i] = add_p(pp, qbar[i], mul_p(pp, wa, qa[i]));
+        for (int sn = 0; sn < S; sn++) {
+            double q[MAXV], Fl[MAXV];
+            for (int v = 0; v < V; v++) q[v] = qa[v * S + sn];
+            for (int j = 0; j < d; j++) {
+                paper_flux(s, cell, q, j, pp, Fl);
+                for (int v = 0; v < V; v++) {
+                    double *f = fbar + ((size_t)j * V + v) * S + sn;
+                    *f = add_p(pp, *f, mul_p(pp, wa, Fl[v]));
+                }
+            }
+        }
+        if (s->c.pde == OR_SWE) {
+            const double g = rp(pp, s->c.params[0]);
+            for (int sn = 0; sn < S; sn++) w->eta[sn] = add_p(pp, qa[0 * S + sn], qa[3 * S + sn]);
+            for (int j = 0; j < d; j++) {
+                apply_dir_p(s, s->D, j, w->eta, w->deta, 1, pp);
+                for (int sn = 0; sn < S; sn++) {
+                    double *nb = nbar + (size_t)(1 + j) * S + sn;
+                    *nb = add_p(pp, *nb, mul_p(pp, wa, mul_p(pp, mul_p(pp, g, qa[0 * S + sn]), w->deta[sn])));
+                }
+            }
+        }
+    }
+    /* face projections (stored in pp) */
+    for (int j = 0; j < d; j++) {
+        int st = stride_of(j, n);
+        for (int side = 0; side < 2; side++) {
+            const double *E = side ? s->F1 : s->F0;
+            for (int v = 0; v < V; v++)
+                for (int sn = 0; sn < S; sn++) {
+                    if (coord(sn, j, n) != 0) continue;
+                    int f = face_of(sn, j, n, d);
+                    size_t o = (((size_t)j * 2 + side) * V + v) * F + f;
+                    fq[o] = contract_p(n, E, qbar + v * S + sn, st, pp);
+                    ff[o] = contract_p(n, E, fbar + ((size_t)j * V + v) * S + sn, st, pp);
+                }
+        }
+    }
+    /* volume integral added to the state (pp) */
+    const double sigma = rp(pp, dt / s->h);
+    for (size_t i = 0; i < VS; i++) Qstar[i] = rp(pp, Q[i]);
+    for (int j = 0; j < d; j++) {
+        apply_dir_p(s, s->Kxi, j, fbar + (size_t)j * VS, w->tmp, V, pp);
+        for (size_t i = 0; i < VS; i++) Qstar[i] = add_p(pp, Qstar[i], mul_p(pp, sigma, w->tmp[i]));
+    }
+    if (s->c.pde == OR_SWE)
+        for (size_t i = 0; i < VS; i++) Qstar[i] = sub_p(pp, Qstar[i], mul_p(pp, sigma, nbar[i]));
+    free(Q0); free(qbar); free(fbar); free(nbar);
+}
+
+/* The corrector kernel of one cell in type pc: Rusanov (well-balanced for
+ * shallow water) flux at each face node from the face data (converted to pc)
+ * and the face integral added to the stored Q* (converted to pc). */
+static void paper_corrector(const or_solver *s, int64_t cell, double dt, int pc, const double *const *blk_q,
+                            const double *const *blk_f, double *Qc)
+{
+    const int n = s->n, S = s->S, V = s->V, d = s->d, F = s->F;
+    const double sigma = rp(pc, dt / s->h), half = 0.5;
+    for (size_t i = 0; i < (size_t)V * S; i++) Qc[i] = rp(pc, Qc[i]);
+    double qm[MAXV], fm[MAXV], qp[MAXV], fpv[MAXV], G[MAXV];
+    double *Gface = (double *)malloc(sizeof(double) * V * F);
+    for (int j = 0; j < d; j++)
+        for (int side = 0; side < 2; side++) {
+            int64_t nb = neighbour(s, cell, j, side ? +1 : -1);
+            int64_t cl = side ? cell : nb, cr = side ? nb : cell;
+            int kl = side ? 0 : 1 + 2 * j + side, kr = side ? 1 + 2 * j + side : 0;
+            const double *Lq = blk_q[kl] + ((size_t)j * 2 + 1) * V * F;
+            const double *Lf = blk_f[kl] + ((size_t)j * 2 + 1) * V * F;
+            const double *Rq = blk_q[kr] + ((size_t)j * 2 + 0) * V * F;
+            const double *Rf = blk_f[kr] + ((size_t)j * 2 + 0) * V * F;
+            for (int f = 0; f < F; f++) {
+                for (int v = 0; v < V; v++) {
+                    qm[v] = rp(pc, Lq[v * F + f]); fm[v] = rp(pc, Lf[v * F + f]);
+                    qp[v] = rp(pc, Rq[v * F + f]); fpv[v] = rp(pc, Rf[v * F + f]);
+                }
+                double sl = paper_max_eig(s, cl, qm, j, pc), sr = paper_max_eig(s, cr, qp, j, pc);
+                double sp = sl > sr ? sl : sr;
+                for (int v = 0; v < V; v++)
+                    G[v] = sub_p(pc, mul_p(pc, half, add_p(pc, fm[v], fpv[v])),
+                                 mul_p(pc, mul_p(pc, half, sp), sub_p(pc, qp[v], qm[v])));
+                if (s->c.pde == OR_SWE) {
+                    double deta = sub_p(pc, add_p(pc, qp[0], qp[3]), add_p(pc, qm[0], qm[3]));
+                    G[0] = sub_p(pc, mul_p(pc, half, add_p(pc, fm[0], fpv[0])), mul_p(pc, mul_p(pc, half, sp), deta));
+                    G[3] = mul_p(pc, half, add_p(pc, fm[3], fpv[3]));
+                    double hbar = mul_p(pc, half, add_p(pc, qm[0], qp[0]));
+                    double dq = mul_p(pc, mul_p(pc, mul_p(pc, half, rp(pc, s->c.params[0])), hbar), deta);
+                    G[1 + j] = side ? add_p(pc, G[1 + j], dq) : sub_p(pc, G[1 + j], dq);
+                }
+                for (int v = 0; v < V; v++) Gface[v * F + f] = G[v];
+            }
+            const double *L = side ? s->L1 : s->L0;
+            for (int v = 0; v < V; v++)
+                for (int sn = 0; sn < S; sn++) {
+                    double t = mul_p(pc, sigma, mul_p(pc, rp(pc, L[coord(sn, j, n)]), Gface[v * F + face_of(sn, j, n, d)]));
+                    Qc[v * S + sn] = side ? sub_p(pc, Qc[v * S + sn], t) : add_p(pc, Qc[v * S + sn], t);
+                }
+        }
+    free(Gface);
+}
+
+static int step_paper(or_solver *s, double t, double dt)
+{
+    (void)t;
+    const size_t VS = (size_t)s->V * s->S;
+    const size_t FS = (size_t)s->d * 2 * s->V * s->F;
+    const int pp = s->c.prec[0], pc = s->c.prec[2];
+    const int pq = s->c.prec_picard >= 0 ? s->c.prec_picard : pp;
+    double *Qn = (double *)malloc(sizeof(double) * s->ncell * VS);
+    double *fq = (double *)malloc(sizeof(double) * s->ncell * FS);
+    double *ff = (double *)malloc(sizeof(double) * s->ncell * FS);
+    if (!Qn || !fq || !ff) { free(Qn); free(fq); free(ff); return -1; }
+#pragma omp parallel
+    {
+        cell_work w;
+        work_alloc(s, &w);
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t c = 0; c < s->ncell; c++) {
+            paper_predictor(s, c, dt, pp, pq, &w, Qn + c * VS, fq + c * FS, ff + c * FS);
+            store_round(s, Qn + c * VS, VS);
+        }
+        work_free(&w);
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t c = 0; c < s->ncell; c++) {
+        const double *bq[1 + 2 * 3], *bf[1 + 2 * 3];
+        bq[0] = fq + c * FS;
+        bf[0] = ff + c * FS;
+        for (int j = 0; j < s->d; j++)
+            for (int side = 0; side < 2; side++) {
+                int64_t nc = neighbour(s, c, j, side ? +1 : -1);
+                bq[1 + 2 * j + side] = fq + nc * FS;
+                bf[1 + 2 * j + side] = ff + nc * FS;
+            }
+        paper_corrector(s, c, dt, pc, bq, bf, Qn + c * VS);
         store_round(s, Qn + c * VS, VS);
     }
     free(fq);
@@ -978,6 +1294,16 @@ int or_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Threads of the OpenMP loops from now on (timing the oracle on one core). */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }
 

@@ -40,6 +40,17 @@
  * the flux format; the lift multiplies format-rounded inputs in FP32.  Time
  * averages, the Picard time operator and all state accumulation stay FP64.
  *
+ * Paper semantics (semantics = OR_SEM_PAPER; Sec. 4.1, each generated kernel
+ * computes in the type it is instantiated for): the predictor kernel (Picard
+ * loop, time averages, face projection, volume integral and its addition to
+ * the state) runs in prec[0], its Picard loop in prec_picard if that is set,
+ * the corrector kernel (Riemann solve, face integral and its addition) in
+ * prec[2]; every arithmetic result, constant and intermediate value inside a
+ * kernel is rounded to the kernel's type (one rounding per operation, no fused
+ * multiply-add), kernel inputs are converted to it and outputs are stored in
+ * it, and the state between the kernels is held in the storage type.  prec[1]
+ * is unused.  Picard predictor, 1-D to 3-D, no point source.
+ *
  * Storage precision (the paper's fourth control, Sec. 3.1): the persistent
  * state is held in that format between grid traversals: the state given to
  * or_set_state, the first sweep's Q* and the corrected state are each rounded
@@ -56,6 +67,7 @@
 enum { OR_ACOUSTIC = 0, OR_ELASTIC = 1, OR_EULER = 2, OR_SWE = 3 };
 enum { OR_FP64 = 0, OR_FP32 = 1, OR_BF16 = 2, OR_FP16 = 3 };
 enum { OR_PICARD = 0, OR_CK = 1 };
+enum { OR_SEM_BUILD = 0, OR_SEM_PAPER = 1 };
 
 typedef struct {
     int dim, order;
@@ -67,6 +79,9 @@ typedef struct {
     int prec[3];      /* emulated precision: predictor, volume, flux */
     int predictor;    /* OR_PICARD, or OR_CK (linear PDEs without a point source) */
     int storage;      /* emulated storage precision of the state between traversals */
+    int semantics;    /* OR_SEM_BUILD (contraction inputs rounded, FP32 accumulation) or
+                         OR_SEM_PAPER (each kernel computes and stores in its type)   */
+    int prec_picard;  /* paper semantics: type of the Picard loop (-1: the predictor's) */
 } or_config;
 
 typedef struct or_solver {
@@ -105,6 +120,7 @@ int or_sample_points(const or_solver *s, int npts, const double *xyz, int var, d
 int or_info(const or_solver *s, int *out);
 double or_cell_size(const or_solver *s);
 int or_num_threads(void);
+void or_set_num_threads(int n);
 int or_adjoint_step(or_solver *s, const double *Qn, double t, double dt, const double *lam,
                     double *mu, double *grad);
 int or_point_weights(const or_solver *s, const double *x, int64_t *cell_out, double *out);

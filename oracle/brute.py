@@ -210,3 +210,30 @@ def fv_swe_step(U, dt, h, g):
         left = np.roll(G - 0.5 * P, 1, axis=ax)      # enters cell i through its left face
         out = out - dt / h * (right - left)
     return out
+
+
+def fv_rusanov_step_typed(U, dt, h, flux, speed, xp, dtype):
+    """First-order Rusanov finite volumes with every operation in one type:
+    U[V, C0, C1] (periodic, already in `dtype`), flux(q, j) and speed(q, j) written
+    with the array library `xp` (numpy, or torch for bfloat16) in that type.  The
+    update visits the faces direction by direction, the lower face (side 0) before
+    the upper one, each face flux G = 1/2 (F- + F+) - (1/2 s)(q+ - q-) with
+    s = max(s-, s+), and adds +- sigma G: the order of operations of a kernel
+    that computes in that type (the paper's semantics)."""
+    half = xp.asarray(0.5, dtype=dtype) if xp is np else xp.tensor(0.5, dtype=dtype)
+    sig = (np.float64(dt) / np.float64(h))
+    sig = np.asarray(sig, dtype=dtype) if xp is np else xp.tensor(float(np.float32(sig)), dtype=dtype)
+    out = U.copy() if xp is np else U.clone()
+    for j in range(U.ndim - 1):
+        ax = 1 + j
+        for side in (0, 1):
+            if side == 0:   # face between the left neighbour (-) and the cell (+)
+                qm, qp = xp.roll(U, 1, ax) if xp is np else xp.roll(U, 1, ax), U
+            else:           # face between the cell (-) and the right neighbour (+)
+                qm, qp = U, (xp.roll(U, -1, ax) if xp is np else xp.roll(U, -1, ax))
+            sm, sp_ = speed(qm, j), speed(qp, j)
+            s = xp.maximum(sm, sp_)
+            G = half * (flux(qm, j) + flux(qp, j)) - (half * s) * (qp - qm)
+            t = sig * G
+            out = out + t if side == 0 else out - t
+    return out
