@@ -27,8 +27,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# MI355X published peaks: FP64 vector (= FP64 matrix) 78.6 TFLOP/s, FP32 157.3
+# TFLOP/s (vector, packed; dense matrix), dense BF16/FP16 matrix 2.5 PFLOP/s,
+# HBM3E 8 TB/s; 1024 SIMDs (256 CUs) at 2.4 GHz.
 PEAK = {"fp64": 78.6e12, "fp32_valu": 157.3e12, "mfma_fp32": 157.3e12, "mfma_bf16": 2.5e15,
         "mfma_fp16": 2.5e15, "hbm": 8.0e12}
+CLOCK_HZ = 2.4e9
+SIMDS = 1024
 TOL = {"fp64": 1e-10, "fp32": 1e-6, "fp16": 1e-3, "bf16": 1e-2}
 HEADLINE = "fp16"
 
@@ -79,9 +84,9 @@ def fused_bytes(d, N, V, face_bytes, q_only):
 
 # Sources that determine the machine code of k_predictor for this workload.
 KERNEL_SOURCES = ("paper_2504_06889_amd/csrc/common.h", "paper_2504_06889_amd/csrc/kernels.h",
-                  "paper_2504_06889_amd/csrc/registry.h",
-                  "paper_2504_06889_amd/csrc/inst_elastic3.hip", "paper_2504_06889_amd/build.py")
-TRAFFIC_FILE = "profiles/k_predictor_elastic3d_n5_64_hbm_traffic.md"
+                  "paper_2504_06889_amd/csrc/registry.h", "paper_2504_06889_amd/csrc/inst_elastic3.hip",
+                  "paper_2504_06889_amd/csrc/inst_euler.hip", "paper_2504_06889_amd/csrc/inst_swe.hip",
+                  "paper_2504_06889_amd/build.py")
 
 
 def kernel_source_hash():
@@ -98,11 +103,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """Per-launch HBM bytes of k_predictor from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary (scaled by a plain copy's counter readings), or {} when the
-    kernel sources have changed since the counters were taken."""
-    path = os.path.join(ROOT, TRAFFIC_FILE)
+def profile_values(path, tag):
+    """Values `tag <variant>: <number>` of a committed rocprofv3 summary under
+    profiles/, or {} when the kernel sources have changed since it was taken (its
+    kernel-source-sha256 line no longer matches)."""
+    path = os.path.join(ROOT, path)
     if not os.path.exists(path):
         return {}
     out, ok = {}, False
@@ -111,10 +116,70 @@ def measured_traffic():
             t = line.strip()
             if t.startswith("kernel-source-sha256:"):
                 ok = t.split(":", 1)[1].strip() == kernel_source_hash()
-            elif t.startswith("traffic-bytes-per-launch"):
-                key, val = t[len("traffic-bytes-per-launch"):].split(":")
-                out[key.strip()] = int(val)
+            elif t.startswith(tag + " "):
+                key, val = t[len(tag):].split(":")
+                out[key.strip()] = float(val)
     return out if ok else {}
+
+
+def measured_traffic(workload="elastic3d_n5_64"):
+    """Per-launch HBM bytes of the fused kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy's counter readings)."""
+    return profile_values("profiles/k_predictor_%s_hbm_traffic.md" % workload, "traffic-bytes-per-launch")
+
+
+def measured_mfma_busy(workload="elastic3d_n5_64"):
+    """SQ_VALU_MFMA_BUSY_CYCLES per launch of the fused kernel (summed over SIMDs)."""
+    return profile_values("profiles/k_predictor_%s_sq_counters.md" % workload, "mfma-busy-cycles-per-launch")
+
+
+def roofline(pde, d, N, V, I, ncell, t, prec, q_only, traffic=None, mfma_busy=None):
+    """Roofline entry of one fused launch (corrector of the previous step + predictor)
+    taking t seconds: the achieved fraction of each published peak the launch's
+    algorithmic work touches -- HBM bytes / 8 TB/s, the matrix-core contraction flops
+    / the format's dense matrix peak (lower formats), the FP64 vector flops / 78.6
+    TFLOP/s (in FP64 every flop) -- and the binding one (largest fraction) as
+    bound/achieved/peak/frac.  design_bound: the launch time if every unit ran at its
+    peak at once (max over units) and, for comparison, the blended sum of the unit
+    times.  traffic: HBM bytes per launch measured with rocprofv3 counters (or None);
+    mfma_busy: SQ_VALU_MFMA_BUSY_CYCLES per launch summed over SIMDs (or None)."""
+    mf, v64, fl = predictor_flops(pde, d, N, V, I)
+    v64 += corrector_flops(d, N, V)
+    hbm = fused_bytes(d, N, V, 8, q_only) * ncell
+    total = (mf + v64 + fl) * ncell
+    fr = {"hbm": hbm / t / PEAK["hbm"]}
+    times = {"hbm": hbm / PEAK["hbm"]}
+    if prec == "fp64":
+        fr["fp64_valu"] = total / t / PEAK["fp64"]
+        times["fp64_valu"] = total / PEAK["fp64"]
+    else:
+        fr["mfma_" + prec] = mf * ncell / t / PEAK["mfma_" + prec]
+        fr["fp64_valu"] = v64 * ncell / t / PEAK["fp64"]
+        times["mfma_" + prec] = mf * ncell / PEAK["mfma_" + prec]
+        times["fp64_valu"] = v64 * ncell / PEAK["fp64"] + fl * ncell / PEAK["fp32_valu"]
+    key = max(fr, key=fr.get)
+    if key == "hbm":
+        achieved, peak, unit = hbm / t / 1e9, PEAK["hbm"] / 1e9, "GB/s"
+        bound = "hbm"
+    elif key.startswith("mfma"):
+        achieved, peak, unit = mf * ncell / t / 1e12, PEAK[key] / 1e12, "TFLOP/s"
+        bound = "mfma"
+    else:
+        work = total if prec == "fp64" else v64 * ncell
+        achieved, peak, unit = work / t / 1e12, PEAK["fp64"] / 1e12, "TFLOP/s"
+        bound = "alu"
+    out = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+           "traffic": traffic, "fractions": fr,
+           "flops_per_launch": total, "mfma_flops_per_launch": (mf * ncell if prec != "fp64" else 0),
+           "fp64_flops_per_launch": total if prec == "fp64" else v64 * ncell,
+           "hbm_bytes_per_launch": hbm, "launch_ms": 1e3 * t,
+           "design_bound": {"max_unit_ms": 1e3 * max(times.values()), "blended_ms": 1e3 * sum(times.values()),
+                            "frac_of_max_unit": max(times.values()) / t}}
+    if traffic:
+        out["traffic_GBps"] = traffic / t / 1e9
+    if mfma_busy is not None:
+        out["mfma_util"] = mfma_busy / (t * CLOCK_HZ * SIMDS)
+    return out
 
 
 def l2(W, h, d, A, B=None):
@@ -123,15 +188,21 @@ def l2(W, h, d, A, B=None):
     return float(torch.sqrt((diff * diff * W[None, None, :]).sum() * h ** d))
 
 
-def cpu_baseline(sc, seconds=12.0, cells=8):
-    """The FP64 oracle on a periodic cells^3 sub-grid of the same problem (same
-    order, cell size and per-cell work), timed on the host cores."""
-    import oracle
-    h = (sc.hi[0] - sc.lo[0]) / sc.cells[0]
-    o = oracle.Oracle(sc.dim, sc.order, (cells,) * sc.dim, sc.lo, tuple(sc.lo[j] + cells * h for j in range(sc.dim)),
-                      sc.pde, sc.params)
-    o.set_state(sc.initial_state(o.node_coords()))
-    dt = o.max_dt(sc.cfl)
+def cpu_model():
+    """Host CPU model name (from /proc/cpuinfo) and the number of logical CPUs."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def _time_oracle(o, dt, seconds):
     o.step(0.0, dt)  # warm-up
     steps, t0 = 0, time.perf_counter()
     while True:
@@ -139,12 +210,70 @@ def cpu_baseline(sc, seconds=12.0, cells=8):
         steps += 1
         el = time.perf_counter() - t0
         if el >= seconds or steps >= 2000:
-            break
+            return steps, el
+
+
+def cpu_baseline(sc, seconds=12.0, cells=8):
+    """The FP64 oracle on a periodic cells^3 sub-grid of the same problem (same
+    order, cell size and per-cell work), timed on the host cores: all threads
+    (value, cores), then one thread for half the time."""
+    import oracle
+    h = (sc.hi[0] - sc.lo[0]) / sc.cells[0]
+    o = oracle.Oracle(sc.dim, sc.order, (cells,) * sc.dim, sc.lo, tuple(sc.lo[j] + cells * h for j in range(sc.dim)),
+                      sc.pde, sc.params)
+    o.set_state(sc.initial_state(o.node_coords()))
+    dt = o.max_dt(sc.cfl)
     dof = o.ncell * o.S * o.V
-    return {"value": dof * steps / el, "unit": "cell-DOF updates/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    steps, el = _time_oracle(o, dt, seconds)
+    oracle.set_num_threads(1)
+    steps1, el1 = _time_oracle(o, dt, 0.5 * seconds)
+    oracle.set_num_threads(cores)
+    model, ncpu = cpu_model()
+    return {"value": dof * steps / el, "unit": "cell-DOF updates/s", "cores": cores,
             "kind": "oracle",
             "sample": "%d FP64 oracle steps of the same problem on a periodic %d^3-cell sub-grid "
-                      "(%d cells, same order and cell size), %.1f s" % (steps, cells, o.ncell, el)}
+                      "(%d cells, same order and cell size), %.1f s on %d threads; one thread: %d steps, %.1f s" % (
+                          steps, cells, o.ncell, el, cores, steps1, el1),
+            "one_thread": {"value": dof * steps1 / el1, "cores": 1},
+            "cpu_model": model, "logical_cpus": ncpu}
+
+
+def golden(name):
+    """The full-length FP64 oracle reference of a workload (tests/golden, written by
+    tests/golden/make_fullsize.py with the oracle only), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "fullsize_%s.npz" % name)
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def vs_oracle(ref, B, W):
+    """Sampled-cell comparison with the oracle reference: relative L2 (eq. L2gauss
+    weights) over the sampled cells, and the largest |B - A| over each variable's
+    largest |A| (both over the sampled cells)."""
+    A = ref["Q"]
+    w = W[None, None, :]
+    rel = float(np.sqrt(((B - A) ** 2 * w).sum() / (A ** 2 * w).sum()))
+    scale = np.abs(A).max(axis=(0, 2))
+    elem = float((np.abs(B - A).max(axis=(0, 2)) / np.where(scale > 0, scale, 1.0)).max())
+    return {"l2_rel_vs_fp64_oracle": rel, "max_rel_vs_fp64_oracle": elem, "cells_sampled": int(A.shape[0]),
+            "steps": int(ref["nsteps"])}
+
+
+def accuracy_run(g, sc, Q0, ref):
+    """The workload's own number of steps from the initial state at the oracle
+    reference's dt, compared with the reference at its sampled cells."""
+    import torch
+    g.set_state(Q0)
+    g.time = 0.0
+    g.step(float(ref["dt"]), int(ref["nsteps"]))
+    ids = torch.from_numpy(ref["ids"]).cuda()
+    st = g.get_state(out=torch.empty(g.shape, dtype=torch.float64, device="cuda"))
+    B = st.index_select(0, ids).cpu().numpy()
+    del st
+    return vs_oracle(ref, B, g.weights())
 
 
 def adjoint_bench(steps=None, checkpoint=None, fd=True, mixed=("fp16", "bf16")):
@@ -242,59 +371,89 @@ def sweep_runs(pde):
     return runs
 
 
-def sweep():
-    """Per-kernel precision sweep on the 3-D Euler density wave (N=4, 48^3 cells, 200
-    steps) and the 2-D shallow-water bump (N=6, 512^2 cells, 500 steps): for every
-    setting the whole run's cell-DOF updates/s and the relative L2 error (eq. L2gauss)
-    of the final state against the FP64 GPU run (parity-checked against the oracle) and,
-    for Euler, against the exact solution."""
+def workload_runs(name):
+    """One workload's precision settings (sweep_runs), each run for the workload's
+    own number of steps from the initial state and timed whole: ms/step, cell-DOF
+    updates/s, the fused kernel's time per launch (HIP events) and its roofline, the
+    relative L2 error (eq. L2gauss) of the final state against the FP64 GPU run, the
+    exact solution (density wave) and, at the sampled cells of the full-length FP64
+    oracle reference (when present), against the oracle."""
     import torch
     from paper_2504_06889_amd import inputs
     from paper_2504_06889_amd.aderdg import NonFiniteError, Solver
-    out = {}
-    for name in ("euler3d_n4_48", "swe2d_n6_512"):
-        sc = inputs.SCENARIOS[name]
-        g = Solver.from_scenario(sc)
-        Q0 = torch.from_numpy(sc.initial_state(g.node_coords())).cuda()
+    sc = inputs.SCENARIOS[name]
+    g = Solver.from_scenario(sc)
+    Q0 = torch.from_numpy(sc.initial_state(g.node_coords())).cuda()
+    g.set_state(Q0)
+    dt = g.max_dt(sc.cfl)
+    ref_o = golden(name)
+    if ref_o is not None and abs(float(ref_o["dt"]) - dt) <= 1e-14 * dt:
+        dt = float(ref_o["dt"])  # the reference's dt (equal up to rounding)
+    else:
+        ref_o = None
+    W = torch.from_numpy(g.weights()).cuda()
+    Wn = g.weights()
+    exact = None
+    if sc.ic == "euler_density_wave":
+        exact = torch.from_numpy(sc.initial_state(g.node_coords(), sc.steps * dt)).cuda()
+    dof = g.ncell * g.S * g.V
+    traffic, busy = measured_traffic(name), measured_mfma_busy(name)
+    ref, runs = None, {}
+    for label, prec in sweep_runs(sc.pde):
+        g.set_precisions(*prec)
         g.set_state(Q0)
-        dt = g.max_dt(sc.cfl)
-        W = torch.from_numpy(g.weights()).cuda()
-        exact = None
-        if sc.ic == "euler_density_wave":
-            exact = torch.from_numpy(sc.initial_state(g.node_coords(), sc.steps * dt)).cuda()
-        dof = g.ncell * g.S * g.V
-        ref, runs = None, {}
-        for label, prec in sweep_runs(sc.pde):
-            g.set_precisions(*prec)
-            g.set_state(Q0)
-            g.time = 0.0
+        g.time = 0.0
+        r = {"precisions": dict(zip(("predictor", "volume", "flux"), prec))}
+        torch.cuda.synchronize()
+        g.set_timing(True)
+        t0 = time.perf_counter()
+        try:
+            g.step(dt, sc.steps)
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = {"precisions": dict(zip(("predictor", "volume", "flux"), prec))}
-            try:
-                g.step(dt, sc.steps)
-                torch.cuda.synchronize()
-                el = time.perf_counter() - t0
-                st = g.get_state(out=torch.empty(g.shape, dtype=torch.float64, device="cuda"))
-            except NonFiniteError as e:
-                r["error"] = "non-finite state: %s" % e
-                runs[label] = r
-                continue
-            if ref is None:
-                ref = st
-            nref = l2(W, g.h, g.d, ref)
-            r.update({"ms_per_step": 1e3 * el / sc.steps, "dof_per_s": dof * sc.steps / el,
-                      "l2_rel_vs_fp64_gpu": l2(W, g.h, g.d, st, ref) / nref})
-            if exact is not None:
-                r["l2_rel_vs_exact"] = l2(W, g.h, g.d, st, exact) / l2(W, g.h, g.d, exact)
+            el = time.perf_counter() - t0
+            tm = g.get_timing()
+            st = g.get_state(out=torch.empty(g.shape, dtype=torch.float64, device="cuda"))
+        except NonFiniteError as e:
+            g.set_timing(False)
+            r["error"] = "non-finite state: %s" % e
             runs[label] = r
-            print("%s %s: %s" % (name, label, ", ".join("%s %.4g" % (k, v) for k, v in r.items()
-                                                       if isinstance(v, float))), file=sys.stderr, flush=True)
-        out[name] = {"steps": sc.steps, "dt": dt, "cells": g.ncell, "order": sc.order, "runs": runs}
-        g.close()
-        del ref, Q0, exact
-        torch.cuda.empty_cache()
+            print("%s %s: non-finite" % (name, label), file=sys.stderr, flush=True)
+            continue
+        g.set_timing(False)
+        if ref is None:
+            ref = st
+        nref = l2(W, g.h, g.d, ref)
+        fused = tm["fused_ms"] / max(tm["fused_launches"], 1)
+        r.update({"ms_per_step": 1e3 * el / sc.steps, "dof_per_s": dof * sc.steps / el, "fused_kernel_ms": fused,
+                  "l2_rel_vs_fp64_gpu": l2(W, g.h, g.d, st, ref) / nref})
+        if exact is not None:
+            r["l2_rel_vs_exact"] = l2(W, g.h, g.d, st, exact) / l2(W, g.h, g.d, exact)
+        if ref_o is not None:
+            ids = torch.from_numpy(ref_o["ids"]).cuda()
+            r.update(vs_oracle(ref_o, st.index_select(0, ids).cpu().numpy(), Wn))
+        # roofline of the fused kernel where the predictor's format sets its kind
+        if prec[0] == prec[1] or prec[0] == "fp64":
+            key = "fp64" if prec == ("fp64",) * 3 else label
+            r["roofline"] = roofline(sc.pde, sc.dim, sc.order, g.V, g.iters, g.ncell, fused * 1e-3,
+                                     prec[0] if prec[0] != "fp64" else "fp64", sc.pde in ("acoustic", "elastic")
+                                     and prec[2] == "fp64", traffic.get(key), busy.get(key))
+        runs[label] = r
+        print("%s %s: %s" % (name, label, ", ".join("%s %.4g" % (k, v) for k, v in r.items()
+                                                   if isinstance(v, float))), file=sys.stderr, flush=True)
+    out = {"workload": "%s: %s, N=%d, %s cells, %d steps, C_CFL=%.2f, dt=%.6e" % (
+               name, sc.pde, sc.order, "x".join(map(str, sc.cells)), sc.steps, sc.cfl, dt),
+           "steps": sc.steps, "dt": dt, "cells": g.ncell, "order": sc.order, "dof_per_step": dof,
+           "oracle_reference": ref_o is not None, "runs": runs}
+    g.close()
+    del ref, Q0, exact
+    torch.cuda.empty_cache()
     return out
+
+
+def sweep():
+    """Per-kernel precision sweep on the 3-D Euler density wave (N=4, 48^3 cells, 200
+    steps) and the 2-D shallow-water bump (N=6, 512^2 cells, 500 steps)."""
+    return {name: workload_runs(name) for name in ("euler3d_n4_48", "swe2d_n6_512")}
 
 
 PAPER_RUNS = [("fp64", ("fp64",) * 3), ("predictor+volume=fp32", ("fp32", "fp32", "fp64")),
@@ -372,6 +531,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the 3-D Euler and 2-D shallow-water precision runs")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the full-length runs compared with the FP64 oracle reference")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--sweep", action="store_true",
                     help="only run the per-kernel precision sweep on the Euler and shallow-water workloads")
@@ -485,30 +648,32 @@ def main():
             if "fp64" in runs:
                 runs[p]["speedup_vs_fp64"] = runs["fp64"]["ms_per_step"] / runs[p]["ms_per_step"]
 
-    # roofline of the dominant kernel (the fused corrector + predictor) for each variant
-    traffic = measured_traffic() if args.workload == "elastic3d_n5_64" else {}
-    I = g.iters
-    mf, v64, fl = predictor_flops(sc.pde, sc.dim, sc.order, g.V, I)
-    v64 += corrector_flops(sc.dim, sc.order, g.V)
+    # roofline of the dominant kernel (the fused corrector + predictor) for each
+    # Picard variant (the counts are the Picard predictor's)
+    traffic, busy = measured_traffic(args.workload), measured_mfma_busy(args.workload)
     for p in runs:
         if runs[p]["predictor"] != "picard":
-            continue  # the roofline counts are the Picard predictor's
-        t = runs[p]["fused_kernel_ms"] * 1e-3
-        total = (mf + v64 + fl) * g.ncell
-        if p == "fp64":
-            ideal = total / PEAK["fp64"]
-            bound = "alu"
-        else:
-            t_m = mf * g.ncell / PEAK["mfma_" + p]
-            t_v = v64 * g.ncell / PEAK["fp64"] + fl * g.ncell / PEAK["fp32_valu"]
-            ideal = t_m + t_v
-            bound = "mfma" if t_m > t_v else "alu"
-        hbm = fused_bytes(sc.dim, sc.order, g.V, 8, sc.pde in ("acoustic", "elastic")) * g.ncell
-        runs[p]["roofline"] = {
-            "bound": bound, "achieved": total / t / 1e12, "peak": total / ideal / 1e12, "unit": "TFLOP/s",
-            "frac": ideal / t, "traffic": traffic.get(p),
-            "flops_per_launch": total, "mfma_flops_per_launch": (mf * g.ncell if p != "fp64" else 0),
-            "hbm_bytes_per_launch": hbm, "hbm_GBps": hbm / t / 1e9}
+            continue
+        runs[p]["roofline"] = roofline(sc.pde, sc.dim, sc.order, g.V, g.iters, g.ncell,
+                                       runs[p]["fused_kernel_ms"] * 1e-3, p, sc.pde in ("acoustic", "elastic"),
+                                       traffic.get(p), busy.get(p))
+
+    # the workload's own number of steps from the initial state, each variant
+    # against the full-length FP64 oracle reference at its sampled cells
+    ref_o = golden(args.workload)
+    if ref_o is not None and not args.no_accuracy:
+        for label, kind, p in labels:
+            prec = ("fp64", "fp64", "fp64") if p == "fp64" else (p, p, "fp64")
+            g.set_predictor(kind)
+            g.set_precisions(*prec)
+            acc = accuracy_run(g, sc, Q0, ref_o)
+            acc["tolerance"] = TOL[p]
+            acc["within_tolerance"] = bool(acc["l2_rel_vs_fp64_oracle"] <= TOL[p])
+            runs[label]["vs_fp64_oracle"] = acc
+            print("%s vs FP64 oracle after %d steps: rel L2 %.3e, max rel %.3e" % (
+                label, acc["steps"], acc["l2_rel_vs_fp64_oracle"], acc["max_rel_vs_fp64_oracle"]),
+                file=sys.stderr, flush=True)
+        g.set_predictor("picard")
 
     g.close()
     del states, Q0, exact
@@ -531,8 +696,13 @@ def main():
         "roofline": r["roofline"],
         "speedup_vs_fp64": r.get("speedup_vs_fp64"),
         "l2_rel_vs_fp64_gpu": r.get("l2_rel_vs_fp64_gpu"), "tolerance": TOL.get(head),
+        "l2_rel_vs_fp64_oracle": r.get("vs_fp64_oracle", {}).get("l2_rel_vs_fp64_oracle"),
         "runs": runs,
     }
+    if not args.no_workloads:
+        line["workloads"] = {}
+        for name in ("euler3d_n4_48", "swe2d_n6_512"):
+            line["workloads"][name] = workload_runs(name)
     if not args.no_adjoint:
         line["adjoint"] = adjoint_bench()
         print("adjoint: %.1f ms forward, %.1f ms backward, ratio %.2f, fd rel err %.2e" % (

@@ -35,17 +35,37 @@ def test_sweep_settings():
     assert swe["predictor+volume=bf16"] == ("bf16", "bf16", "fp64") and swe["all=fp32"] == ("fp32",) * 3
 
 
-def test_traffic_only_for_profiled_sources(tmp_path, monkeypatch):
-    src = os.path.join(ROOT, bench.TRAFFIC_FILE)
+def test_profile_values_only_for_profiled_sources(tmp_path):
+    src = os.path.join(ROOT, "profiles", "k_predictor_elastic3d_n5_64_hbm_traffic.md")
     if not os.path.exists(src):
         pytest.skip("no traffic summary committed")
     text = open(src).read()
     fake = tmp_path / "traffic.md"
     fake.write_text(text.replace("kernel-source-sha256: ", "kernel-source-sha256: 0"))
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(fake))
-    assert bench.measured_traffic() == {}
+    assert bench.profile_values(str(fake), "traffic-bytes-per-launch") == {}
     fake.write_text("\n".join(l if not l.strip().startswith("kernel-source-sha256:")
                               else "    kernel-source-sha256: " + bench.kernel_source_hash()
                               for l in text.split("\n")))
-    t = bench.measured_traffic()
+    t = bench.profile_values(str(fake), "traffic-bytes-per-launch")
     assert set(t) == {"fp64", "fp32", "bf16", "fp16"} and all(v > 0 for v in t.values())
+
+
+def test_roofline_fractions_of_published_peaks():
+    """The binding fraction is the largest of HBM bytes / 8 TB/s, matrix-core flops /
+    the format's dense peak and FP64 vector flops / 78.6 TFLOP/s; each is recomputable
+    from the counts and the launch time."""
+    d, N, V, I, ncell, t = 3, 5, 9, 6, 64 ** 3, 16.7e-3
+    mf, v64, fl = bench.predictor_flops("elastic", d, N, V, I)
+    v64 += bench.corrector_flops(d, N, V)
+    r = bench.roofline("elastic", d, N, V, I, ncell, t, "fp16", True, traffic=2e10, mfma_busy=3.6e9)
+    hbm = bench.fused_bytes(d, N, V, 8, True) * ncell
+    assert abs(r["fractions"]["hbm"] - hbm / t / 8e12) < 1e-12
+    assert abs(r["fractions"]["mfma_fp16"] - mf * ncell / t / 2.5e15) < 1e-12
+    assert abs(r["fractions"]["fp64_valu"] - v64 * ncell / t / 78.6e12) < 1e-12
+    key = max(r["fractions"], key=r["fractions"].get)
+    assert abs(r["frac"] - r["fractions"][key]) < 1e-12
+    assert abs(r["achieved"] / r["peak"] - r["frac"]) < 1e-12
+    assert abs(r["mfma_util"] - 3.6e9 / (t * 2.4e9 * 1024)) < 1e-12
+    r64 = bench.roofline("elastic", d, N, V, I, ncell, 33.6e-3, "fp64", True)
+    assert r64["bound"] == "alu" and r64["unit"] == "TFLOP/s"
+    assert abs(r64["achieved"] * 1e12 - (mf + v64 + fl) * ncell / 33.6e-3) < 1e-3 * r64["achieved"] * 1e12
