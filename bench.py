@@ -465,57 +465,102 @@ PAPER_RUNS = [("fp64", ("fp64",) * 3), ("predictor+volume=fp32", ("fp32", "fp32"
               ("all+storage=fp16", ("fp16",) * 4)]
 
 
-def paper_suite():
-    """The paper's 2-D scenarios of its mixed-precision study (27^2 cells, order 5, run to
-    t_end) with the state in FP64 and the predictor and volume contractions, the face
-    kernels, or all of them in a lower format (the paper's one-kernel-at-a-time design),
-    and with every kernel and the stored state in the format:
+def paper_table_runs():
+    """Settings (predictor, volume, flux, storage) of the paper's two tables of one
+    kernel changed against a base (Sec. 7), mapped to this library's knobs: the
+    paper's "Picard" kernel is PREDICTOR (the Picard contractions), its "predictor"
+    kernel PREDICTOR + VOLUME (its fused predictor computes the volume integral), its
+    "corrector" FLUX, "all" every kernel.
+      fp32-storage table: state and every kernel FP32, one kernel (or all) in BF16
+        or FP16;
+      higher-fp64 table: state and every kernel in a base format (BF16, FP16,
+        FP32), one kernel (or all kernels) in FP64."""
+    def one(kernel, p, base):
+        pr, vo, fl = base, base, base
+        if kernel == "Picard":
+            pr = p
+        elif kernel == "predictor":
+            pr = vo = p
+        elif kernel == "corrector":
+            fl = p
+        elif kernel == "all":
+            pr = vo = fl = p
+        return (pr, vo, fl, base)
+    runs = [("storage32:reference", ("fp32",) * 4)]
+    for p in ("bf16", "fp16"):
+        for k in ("Picard", "predictor", "corrector", "all"):
+            runs.append(("storage32:%s=%s" % (k, p), one(k, p, "fp32")))
+    for base in ("bf16", "fp16", "fp32"):
+        runs.append(("base%s:reference" % base[2:], (base,) * 4))
+        for k in ("Picard", "predictor", "corrector", "all"):
+            runs.append(("base%s:%s=fp64" % (base[2:], k), one(k, "fp64", base)))
+    return runs
+
+
+def paper_suite_runs(sc, settings, label_prefix=""):
+    """Run the settings (predictor, volume, flux[, storage]) of a 2-D scenario to t_end:
     the L2 error of eq. L2gauss against the interpolant of the exact solution at t_end,
     absolute (as the paper reports it) and relative, the relative L2 difference to the
     FP64 GPU run and, for the lake at rest, the largest spurious momentum."""
     import torch
-    from paper_2504_06889_amd import inputs
     from paper_2504_06889_amd.aderdg import NonFiniteError, Solver
-    out = {}
-    for name, sc in inputs.PAPER_SUITE.items():
-        g = Solver.from_scenario(sc)
-        X = g.node_coords()
-        Q0 = torch.from_numpy(sc.initial_state(X)).cuda()
+    g = Solver.from_scenario(sc)
+    X = g.node_coords()
+    Q0 = torch.from_numpy(sc.initial_state(X)).cuda()
+    g.set_state(Q0)
+    t_end = sc.extra["t_end"]
+    nsteps = int(math.ceil(t_end / g.max_dt(sc.cfl)))
+    dt = t_end / nsteps
+    W = torch.from_numpy(g.weights()).cuda()
+    exact = torch.from_numpy(sc.initial_state(X, t_end)).cuda()
+    nex = l2(W, g.h, g.d, exact)
+    ref, runs = None, {}
+    for label, prec in [("fp64", ("fp64",) * 4)] + list(settings):
+        prec = tuple(prec) + ("fp64",) * (4 - len(prec))
+        g.set_precision("storage", prec[3])
+        g.set_precisions(*prec[:3])
         g.set_state(Q0)
-        t_end = sc.extra["t_end"]
-        nsteps = int(math.ceil(t_end / g.max_dt(sc.cfl)))
-        dt = t_end / nsteps
-        W = torch.from_numpy(g.weights()).cuda()
-        exact = torch.from_numpy(sc.initial_state(X, t_end)).cuda()
-        nex = l2(W, g.h, g.d, exact)
-        ref, runs = None, {}
-        for label, prec in PAPER_RUNS:
-            g.set_precision("storage", prec[3] if len(prec) > 3 else "fp64")
-            g.set_precisions(*prec[:3])
-            g.set_state(Q0)
-            g.time = 0.0
-            r = {"precisions": dict(zip(("predictor", "volume", "flux", "storage"), tuple(prec) + ("fp64",) * (4 - len(prec))))}
-            try:
-                g.step(dt, nsteps)
-                st = g.get_state(out=torch.empty(g.shape, dtype=torch.float64, device="cuda"))
-            except NonFiniteError as e:
-                r["error"] = "non-finite state: %s" % e
-                runs[label] = r
-                print("%s %s: non-finite" % (name, label), file=sys.stderr, flush=True)
-                continue
-            if ref is None:
-                ref = st
-            r["l2_vs_exact"] = l2(W, g.h, g.d, st, exact)
-            r["l2_rel_vs_exact"] = r["l2_vs_exact"] / nex
-            r["l2_rel_vs_fp64_gpu"] = l2(W, g.h, g.d, st, ref) / l2(W, g.h, g.d, ref)
-            if sc.pde == "swe":
-                r["max_abs_momentum"] = float(st[:, 1:3].abs().max())
+        g.time = 0.0
+        r = {"precisions": dict(zip(("predictor", "volume", "flux", "storage"), prec))}
+        try:
+            g.step(dt, nsteps)
+            st = g.get_state(out=torch.empty(g.shape, dtype=torch.float64, device="cuda"))
+        except NonFiniteError as e:
+            r["error"] = "non-finite state: %s" % e
             runs[label] = r
-            print("%s %s: %s" % (name, label, ", ".join("%s %.3g" % (k, v) for k, v in r.items()
-                                                       if isinstance(v, float))), file=sys.stderr, flush=True)
-        out[name] = {"cells": list(sc.cells), "order": sc.order, "t_end": t_end, "steps": nsteps, "dt": dt,
-                     "runs": runs}
-        g.close()
+            print("%s %s: non-finite" % (sc.name, label), file=sys.stderr, flush=True)
+            continue
+        if ref is None:
+            ref = st
+        r["l2_vs_exact"] = l2(W, g.h, g.d, st, exact)
+        r["l2_rel_vs_exact"] = r["l2_vs_exact"] / nex
+        r["l2_rel_vs_fp64_gpu"] = l2(W, g.h, g.d, st, ref) / l2(W, g.h, g.d, ref)
+        if sc.pde == "swe":
+            r["max_abs_momentum"] = float(st[:, 1:3].abs().max())
+        runs[label] = r
+        print("%s %s: %s" % (sc.name, label, ", ".join("%s %.3g" % (k, v) for k, v in r.items()
+                                                      if isinstance(v, float))), file=sys.stderr, flush=True)
+    g.close()
+    return {"cells": list(sc.cells), "order": sc.order, "t_end": t_end, "steps": nsteps, "dt": dt, "runs": runs}
+
+
+def paper_suite():
+    """The paper's 2-D scenarios of its mixed-precision study (27^2 cells, order 5, run to
+    t_end): the state in FP64 with the predictor and volume contractions, the face
+    kernels, or all of them in a lower format (the paper's one-kernel-at-a-time
+    design) and every kernel and the stored state in the format; the settings of the
+    paper's FP32-storage table and of its table of one kernel in FP64 on a lower base;
+    and the two Euler scenarios on 81^2 cells with an FP32 base and one kernel in FP64
+    (the paper's finer-grid table)."""
+    from paper_2504_06889_amd import inputs
+    out = {}
+    table = paper_table_runs()
+    for name, sc in inputs.PAPER_SUITE.items():
+        out[name] = paper_suite_runs(sc, PAPER_RUNS[1:] + table)
+    for name in ("euler2d_n5_27_bell", "euler2d_n5_27_vortex"):
+        sc = inputs.PAPER_SUITE[name].with_cells((81, 81))
+        fine = [(k, p) for k, p in table if k.startswith("base32:")]
+        out[name.replace("_27_", "_81_")] = paper_suite_runs(sc, fine)
     return out
 
 
@@ -692,7 +737,7 @@ def main():
                                    sc.name, "all contractions FP64 on the vector ALU" if head == "fp64" else
                                    "predictor+volume contractions in %s on matrix cores (FP32 accumulate)" % head,
                                    sc.cfl, dt),
-                   "cells": g.ncell, "order": sc.order, "dof_per_step": dof, "picard_iters": I},
+                   "cells": g.ncell, "order": sc.order, "dof_per_step": dof, "picard_iters": g.iters},
         "roofline": r["roofline"],
         "speedup_vs_fp64": r.get("speedup_vs_fp64"),
         "l2_rel_vs_fp64_gpu": r.get("l2_rel_vs_fp64_gpu"), "tolerance": TOL.get(head),

@@ -3,10 +3,10 @@
  *
  * The library advances hyperbolic systems q_t + div F(q) + B(q) grad q = S on a
  * periodic Cartesian grid with the ADER-DG one-step scheme of arXiv 2504.06889,
- * Sec. 2: a cell-local space-time predictor (eq. Picard, solved by Picard
+ * Sec. 3: a cell-local space-time predictor (eq. Picard, solved by Picard
  * iteration), the volume integral and the surface integral of the Rusanov
  * numerical flux (eq. weak_form_volume_surface, eq. rusanov_flux), in the
- * order of Alg. 1.  Per-kernel precision follows Sec. 3.1 (the "predictor",
+ * order of Alg. 1.  Per-kernel precision follows Sec. 4.1 (the "predictor",
  * "corrector" and "storage" controls), remapped as described below.
  *
  * Conventions
@@ -46,19 +46,20 @@ typedef enum {
 
 typedef enum { ADERDG_ACOUSTIC = 0, ADERDG_ELASTIC = 1, ADERDG_EULER = 2, ADERDG_SWE = 3 } aderdg_pde;
 
-/* Kernels whose contractions take a precision (Sec. 3.1, four controls):
+/* Kernels whose contractions take a precision (Sec. 4.1, four controls):
  *   PREDICTOR - the Picard iteration's spatial-derivative contractions (the
  *               paper's "predictor" and "Picard" controls; Picard is used for
  *               every PDE here);
  *   VOLUME    - the volume-integral contraction;
  *   FLUX      - face projection, face-value storage, Riemann solve and lift
  *               (the paper's "corrector"; the update Q += dt (...) stays FP64);
- *   STORAGE   - the persistent state held between traversals (the state
- *               given to set_state, Q* after the predictor, the corrected
- *               state) is rounded to that format (FP32 first, then the
- *               format) each time it is stored; it stays in FP64 containers
- *               (same layout and footprint); all arithmetic is unchanged.
- *               Default FP64.
+ *   STORAGE   - the format of the persistent state held in device memory
+ *               between traversals (the state given to set_state, Q* after
+ *               the predictor, the corrected state): FP64 (default), or
+ *               FP32/BF16/FP16 elements (8/4/2 bytes, same layout), each
+ *               value rounded to the format (FP32 first, then the format)
+ *               when it is stored and widened exactly when it is read; all
+ *               arithmetic is unchanged.  get/set_state still take FP64.
  * In a lower precision the contraction inputs (data and matrix) are rounded
  * to that format (round-to-nearest-even) and the products are accumulated in
  * FP32 (matrix cores for PREDICTOR and VOLUME); the Picard time operator, the
@@ -66,7 +67,7 @@ typedef enum { ADERDG_ACOUSTIC = 0, ADERDG_ELASTIC = 1, ADERDG_EULER = 2, ADERDG
 typedef enum { ADERDG_K_PREDICTOR = 0, ADERDG_K_VOLUME = 1, ADERDG_K_FLUX = 2, ADERDG_K_STORAGE = 3 } aderdg_kernel;
 typedef enum { ADERDG_FP64 = 0, ADERDG_FP32 = 1, ADERDG_BF16 = 2, ADERDG_FP16 = 3 } aderdg_prec;
 
-/* Space-time predictor (Sec. 2): the Picard iteration of eq. Picard, or, for
+/* Space-time predictor (Sec. 3): the Picard iteration of eq. Picard, or, for
  * linear PDEs, the Cauchy-Kowalevskaya procedure the paper names as the
  * cheaper alternative (time derivatives from the PDE, Taylor expansion to
  * degree N in time).                                                         */
@@ -84,7 +85,7 @@ typedef struct {
     int picard_iters; /* Picard iterations per step; 0 -> N+1                         */
 } aderdg_config;
 
-/* Create a solver (Sec. 2 scheme on the given grid).  Builds the
+/* Create a solver (Sec. 3 scheme on the given grid).  Builds the
  * Gauss-Legendre basis and operators on the host in FP64, allocates the state
  * (zero), face buffers and constants on the current HIP device.  `hip_stream`
  * is a hipStream_t (may be NULL).  Errors: INVALID (bad config, 2^31 or more
@@ -118,9 +119,11 @@ aderdg_status aderdg_set_material(aderdg_solver *s, const double *c, int is_devi
 aderdg_status aderdg_set_predictor(aderdg_solver *s, int kind);
 
 /* Select the precision of one kernel's contractions, or the storage precision
- * of the state (see aderdg_kernel).  Setting STORAGE rounds the state held now
- * to it.  Errors: INVALID (unknown kernel/precision), UNSUPPORTED (predictor
- * format not built), DEVICE.  The adjoint needs FP64 storage.                */
+ * of the state (see aderdg_kernel).  Setting STORAGE moves the state held now
+ * into a new buffer of that format, rounding each value (synchronises the
+ * stream; the old buffer is freed).  Errors: INVALID (unknown
+ * kernel/precision), UNSUPPORTED (predictor format not built), OOM, DEVICE.
+ * The adjoint needs FP64 storage.                                            */
 aderdg_status aderdg_set_precision(aderdg_solver *s, int kernel, int prec);
 
 /* Largest admissible time step of eq. CFL_condition,
@@ -187,8 +190,11 @@ aderdg_status aderdg_copy_faces(aderdg_solver *s, void *dst, int is_device);
 aderdg_status aderdg_step_adjoint_faces(aderdg_solver *s, double dt, double t, const double *Qn_dev,
                                         const void *fwd_faces_dev, double *lam_dev, double *grad_dev);
 
-/* Scatter the receiver misfit gradient: lam[cell][0][node] += sum_r
- * weight[r] * phi_node(x_r) over receivers in that cell (device pointers). */
+/* Scatter the receiver misfit gradient (the transpose of the receiver
+ * read-out): lam[cell][0][node] += sum_r weight[r] * phi_node(x_r) over the
+ * receivers in that cell (device pointers: weight[nrec], lam in the state
+ * layout).  Each cell's receivers are summed in a fixed order (by receiver
+ * index), so repeated calls give bitwise-equal results.                     */
 aderdg_status aderdg_receivers_adjoint(aderdg_solver *s, const double *weight_dev, double *lam_dev);
 
 /* Gauss-Legendre nodes xi[n] and weights w[n] on [0,1] (the library's basis). */
@@ -198,7 +204,9 @@ aderdg_status aderdg_nodes(int n, double *xi, double *w);
  * cells (total), face buffer bytes per cell.                                */
 aderdg_status aderdg_info(const aderdg_solver *s, long long *info);
 
-/* Device pointer of the state (for zero-copy use by the caller; stream-ordered). */
+/* Device pointer of the state (for zero-copy use by the caller; stream-ordered).
+ * Errors: UNSUPPORTED while the state is held in a storage format other than
+ * FP64 (use aderdg_get_state, which widens it).                              */
 aderdg_status aderdg_state_ptr(aderdg_solver *s, double **dev_ptr);
 
 /* Kernel timing: when enabled, every launch of aderdg_step is bracketed by

@@ -1,4 +1,4 @@
-"""FP64 CPU oracle of the ADER-DG time step (arXiv 2504.06889, Sec. 2).
+"""FP64 CPU oracle of the ADER-DG time step (arXiv 2504.06889, Sec. 3).
 
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` may import this package.  The product library
@@ -102,7 +102,7 @@ def round_p(p, x):
 
 
 def basis(n):
-    """Gauss-Legendre nodes/weights on [0,1] and the derived operators (Sec. 2).
+    """Gauss-Legendre nodes/weights on [0,1] and the derived operators (Sec. 3).
 
     D[i, j] = psi_j'(xi_i); F0/F1 = psi(0)/psi(1); K1 = the time matrix of
     eq. Picard; Atau = K1^{-1} diag(w); Kxi[k, l] = w_l D[l, k] / w_k (weak-form

@@ -6,7 +6,7 @@
  * table or helper with the GPU library under paper_2504_06889_amd/, and the GPU
  * library never loads it.
  *
- * Method: arXiv 2504.06889, Sec. 2 ("The ADER-DG method").
+ * Method: arXiv 2504.06889, Sec. 3 ("The ADER-DG method").
  *   - Nodal tensor-product Lagrange basis on Gauss-Legendre support points
  *     (eq. piecewise_solution, and the text after eq. discreteFlux).
  *   - Predictor: the cell-local space-time DG system of eq. Picard, solved by
@@ -202,7 +202,7 @@ int or_basis(int n, double *xi, double *w, double *D, double *F0, double *F1,
 }
 
 /* ------------------------------------------------------------------------ */
-/* PDE systems (Sec. 4): flux, largest |eigenvalue|, non-conservative part. */
+/* PDE systems (Sec. 5): flux, largest |eigenvalue|, non-conservative part. */
 /* ------------------------------------------------------------------------ */
 
 int or_nvars(int pde, int dim)

@@ -1,5 +1,5 @@
 /*
- * FP64 CPU oracle of the ADER-DG time step (arXiv 2504.06889, Sec. 2).
+ * FP64 CPU oracle of the ADER-DG time step (arXiv 2504.06889, Sec. 3).
  *
  * TEST INFRASTRUCTURE ONLY: used by the test suite, the smoke check and the
  * benchmark's CPU-baseline leg.  Independent of the GPU library (no shared
@@ -26,7 +26,7 @@
  *   - point source (acoustics only): s(t) delta(x - xs) in the pressure
  *     equation, s a Ricker wavelet, included in predictor and corrector;
  *   - Cauchy-Kowalevskaya predictor (linear PDEs, the paper's alternative to
- *     the Picard iteration, Sec. 2): the Taylor expansion of the cell-local
+ *     the Picard iteration, Sec. 3): the Taylor expansion of the cell-local
  *     solution in time to degree N, its time derivatives taken from the PDE
  *     (d/dt = minus the discrete divergence, applied repeatedly); the time
  *     average of the truncated expansion replaces the Picard time average.
@@ -51,7 +51,7 @@
  * it, and the state between the kernels is held in the storage type.  prec[1]
  * is unused.  Picard predictor, 1-D to 3-D, no point source.
  *
- * Storage precision (the paper's fourth control, Sec. 3.1): the persistent
+ * Storage precision (the paper's fourth control, Sec. 4.1): the persistent
  * state is held in that format between grid traversals: the state given to
  * or_set_state, the first sweep's Q* and the corrected state are each rounded
  * to it (FP32 first, then the format); all arithmetic stays as above.

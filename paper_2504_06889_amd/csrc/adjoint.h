@@ -37,7 +37,9 @@ struct AdjointWork {
 
 int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::string &msg);
 void adjoint_free(AdjointWork &w);
-void receivers_adjoint(double *lam, int V, int S, int n, int dim, int nrec, const long *rcell, const double *rphi,
-                       const double *weight, hipStream_t st);
+// Receiver misfit scatter, grouped by cell: ncells cells ucell[m] hold the
+// receivers order[start[m] .. start[m+1]-1].
+void receivers_adjoint(double *lam, int V, int S, int n, int dim, int ncells, const long *ucell, const int *start,
+                       const int *order, const double *rphi, const double *weight, hipStream_t st);
 
 }  // namespace aderdg

@@ -15,24 +15,32 @@
 
 namespace aderdg {
 
-// lam[cell_r][0][s] += weight[r] * prod_j phi[r][j][i_j(s)]  (one thread per receiver and node)
-__global__ void k_receivers_adjoint(double *lam, int V, int S, int n, int dim, int nrec, const long *rcell,
-                                    const double *rphi, const double *weight) {
+// lam[cell][0][s] += sum over the receivers r in that cell of
+// weight[r] * prod_j phi[r][j][i_j(s)]: one thread per (receiver cell, node),
+// the receivers of a cell summed in a fixed order (sorted by cell, then by
+// index), so the result does not depend on scheduling (no atomics).
+__global__ void k_receivers_adjoint(double *lam, int V, int S, int n, int dim, int ncells, const long *ucell,
+                                    const int *start, const int *order, const double *rphi, const double *weight) {
     const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (i >= (long)nrec * S) return;
-    const int r = i / S, s = i % S;
-    const double *ph = rphi + (long)r * 3 * kMaxN;
-    double w = ph[s % n];
-    if (dim > 1) w *= ph[kMaxN + (s / n) % n];
-    if (dim > 2) w *= ph[2 * kMaxN + s / (n * n)];
-    atomicAdd(lam + rcell[r] * V * S + s, weight[r] * w);
+    if (i >= (long)ncells * S) return;
+    const int m = i / S, s = i % S;
+    double acc = 0.0;
+    for (int k = start[m]; k < start[m + 1]; k++) {
+        const int r = order[k];
+        const double *ph = rphi + (long)r * 3 * kMaxN;
+        double w = ph[s % n];
+        if (dim > 1) w *= ph[kMaxN + (s / n) % n];
+        if (dim > 2) w *= ph[2 * kMaxN + s / (n * n)];
+        acc = fma(weight[r], w, acc);
+    }
+    lam[ucell[m] * V * S + s] += acc;
 }
 
-void receivers_adjoint(double *lam, int V, int S, int n, int dim, int nrec, const long *rcell, const double *rphi,
-                       const double *weight, hipStream_t st) {
-    const long total = (long)nrec * S;
-    hipLaunchKernelGGL(k_receivers_adjoint, dim3((total + 255) / 256), dim3(256), 0, st, lam, V, S, n, dim, nrec,
-                       rcell, rphi, weight);
+void receivers_adjoint(double *lam, int V, int S, int n, int dim, int ncells, const long *ucell, const int *start,
+                       const int *order, const double *rphi, const double *weight, hipStream_t st) {
+    const long total = (long)ncells * S;
+    hipLaunchKernelGGL(k_receivers_adjoint, dim3((total + 255) / 256), dim3(256), 0, st, lam, V, S, n, dim, ncells,
+                       ucell, start, order, rphi, weight);
 }
 
 using LamFaceFn = void (*)(const double *, double *, long, const DevBasis *, hipStream_t);

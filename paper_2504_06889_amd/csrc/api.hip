@@ -1,6 +1,7 @@
 // C ABI of the ADER-DG library (declared in include/aderdg.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -40,32 +41,34 @@ const KernelSet *find_kernels(int pde, int dim, int order) {
 // ---------------------------------------------------------------------------
 __global__ void k_fill_u64(unsigned long long *p, unsigned long long v) { *p = v; }
 __global__ void k_fill_i32(int *p, int v) { *p = v; }
-// Round the held state to its storage precision, in place.
-__global__ __launch_bounds__(256) void k_round_state(double *Q, long n, int sp) {
-    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) Q[i] = round_q(Q[i], sp);
+// Convert a state between storage precisions (FP64 in or out, or both in the
+// held format): dst[i] = src[i] rounded to the destination format.
+__global__ __launch_bounds__(256) void k_convert_state(const void *src, int sp_src, void *dst, int sp_dst, long n) {
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+        store_state(dst, i, load_state(src, i, sp_src), sp_dst);
 }
 
-__global__ __launch_bounds__(256) void k_nonfinite(const double *x, long n, int *flag) {
+__global__ __launch_bounds__(256) void k_nonfinite(const void *x, int sp, long n, int *flag) {
     int bad = 0;
     for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256)
-        bad |= !isfinite(x[i]);
+        bad |= !isfinite(load_state(x, i, sp));
     bad = __syncthreads_or(bad);
     if (threadIdx.x == 0 && bad) atomicOr(flag, 1);
 }
 
 // p_h(x_r) = sum_s prod_j phi[r][j][i_j(s)] Q[cell_r][0][s]
-__global__ void k_receivers(const double *Q, int V, int S, int n, int dim, int nrec, const long *rcell,
+__global__ void k_receivers(const void *Q, int sp, int V, int S, int n, int dim, int nrec, const long *rcell,
                             const double *rphi, double *out) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrec) return;
-    const double *q = Q + rcell[r] * V * S;
+    const long q0 = rcell[r] * V * S;
     const double *ph = rphi + (long)r * 3 * kMaxN;
     double acc = 0.0;
     for (int s = 0; s < S; s++) {
         double w = ph[s % n];
         if (dim > 1) w *= ph[kMaxN + (s / n) % n];
         if (dim > 2) w *= ph[2 * kMaxN + s / (n * n)];
-        acc += w * q[s];
+        acc += w * load_state(Q, q0 + s, sp);
     }
     out[r] = acc;
 }
@@ -82,7 +85,7 @@ struct aderdg_solver {
     const KernelSet *ks;
     DevBasis hB;
     DevBasis *dB = nullptr;
-    double *dQ = nullptr;
+    void *dQ = nullptr;         // state in the storage precision prec[ADERDG_K_STORAGE]
     void *dFaces = nullptr;     // face data of the last predictor
     void *dFaces2 = nullptr;    // second buffer: a fused step reads one and writes the other
     size_t face_elems = 0;
@@ -93,6 +96,10 @@ struct aderdg_solver {
     int nrec = 0;
     long *dRecCell = nullptr;
     double *dRecPhi = nullptr;
+    // receivers grouped by cell (for the deterministic adjoint scatter)
+    int nrec_cells = 0;
+    long *dRecUcell = nullptr;
+    int *dRecStart = nullptr, *dRecOrder = nullptr;
     unsigned long long *dScalar = nullptr;
     int *dFlag = nullptr;
     int prec[4] = {0, 0, 0, 0};
@@ -132,6 +139,9 @@ static void free_all(aderdg_solver *s) {
     hipFree(s->dSrcPhi);
     hipFree(s->dRecCell);
     hipFree(s->dRecPhi);
+    hipFree(s->dRecUcell);
+    hipFree(s->dRecStart);
+    hipFree(s->dRecOrder);
     hipFree(s->dScalar);
     hipFree(s->dFlag);
     adjoint_free(s->adj);
@@ -249,29 +259,41 @@ static long grid256(long n) {
     return g < 8192 ? g : 8192;
 }
 
-// Round the held state to the storage precision (nothing to do in FP64).
-static void round_state(aderdg_solver *s) {
-    const int sp = s->prec[ADERDG_K_STORAGE];
-    if (sp != ADERDG_FP64)
-        hipLaunchKernelGGL(k_round_state, dim3(grid256(state_elems(s))), dim3(256), 0, s->stream, s->dQ,
-                           state_elems(s), sp);
+static int storage(const aderdg_solver *s) { return s->prec[ADERDG_K_STORAGE]; }
+
+// FP64 staging for host copies of a narrow state: the second face buffer (its
+// contents are only read by the fused launches inside one aderdg_step call,
+// and it holds at least a state's doubles: 4d/n >= 1 for n <= 8).
+static void *staging(aderdg_solver *s) { return s->dFaces2; }
+
+static void convert_state(aderdg_solver *s, const void *src, int sp_src, void *dst, int sp_dst) {
+    hipLaunchKernelGGL(k_convert_state, dim3(grid256(state_elems(s))), dim3(256), 0, s->stream, src, sp_src, dst,
+                       sp_dst, state_elems(s));
 }
 
 aderdg_status aderdg_set_state(aderdg_solver *s, const double *Q, int is_device) {
     if (!s) return ADERDG_E_INVALID;
     if (!Q) FAIL(s, ADERDG_E_INVALID, "null state pointer");
     const size_t bytes = sizeof(double) * state_elems(s);
-    HIPC(s, hipMemcpyAsync(s->dQ, Q, bytes, is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
-    round_state(s);
+    if (storage(s) == ADERDG_FP64) {
+        HIPC(s, hipMemcpyAsync(s->dQ, Q, bytes, is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                               s->stream));
+    } else if (is_device) {
+        convert_state(s, Q, ADERDG_FP64, s->dQ, storage(s));
+    } else {
+        HIPC(s, hipMemcpyAsync(staging(s), Q, bytes, hipMemcpyHostToDevice, s->stream));
+        convert_state(s, staging(s), ADERDG_FP64, s->dQ, storage(s));
+    }
+    HIPC(s, hipGetLastError());
     if (!is_device) HIPC(s, hipStreamSynchronize(s->stream));
     return ADERDG_OK;
 }
-static aderdg_status check_finite(aderdg_solver *s, const double *x, long count, bool *ok) {
+static aderdg_status check_finite(aderdg_solver *s, const void *x, int sp, long count, bool *ok) {
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, s->stream, s->dFlag, 0);
     long g = (count + 255) / 256;
     if (g > 8192) g = 8192;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_nonfinite, dim3(g), dim3(256), 0, s->stream, x, count, s->dFlag);
+    hipLaunchKernelGGL(k_nonfinite, dim3(g), dim3(256), 0, s->stream, x, sp, count, s->dFlag);
     int flag = 0;
     HIPC(s, hipMemcpyAsync(&flag, s->dFlag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
     HIPC(s, hipStreamSynchronize(s->stream));
@@ -283,10 +305,17 @@ aderdg_status aderdg_get_state(aderdg_solver *s, double *Q, int is_device) {
     if (!s) return ADERDG_E_INVALID;
     if (!Q) FAIL(s, ADERDG_E_INVALID, "null state pointer");
     const size_t bytes = sizeof(double) * state_elems(s);
-    HIPC(s, hipMemcpyAsync(Q, s->dQ, bytes, is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                           s->stream));
+    if (storage(s) == ADERDG_FP64) {
+        HIPC(s, hipMemcpyAsync(Q, s->dQ, bytes, is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                               s->stream));
+    } else if (is_device) {
+        convert_state(s, s->dQ, storage(s), Q, ADERDG_FP64);
+    } else {
+        convert_state(s, s->dQ, storage(s), staging(s), ADERDG_FP64);
+        HIPC(s, hipMemcpyAsync(Q, staging(s), bytes, hipMemcpyDeviceToHost, s->stream));
+    }
     bool ok = true;
-    aderdg_status st = check_finite(s, s->dQ, state_elems(s), &ok);
+    aderdg_status st = check_finite(s, s->dQ, storage(s), state_elems(s), &ok);
     if (st != ADERDG_OK) return st;
     if (!ok) FAIL(s, ADERDG_E_NONFINITE, "state holds NaN or Inf");
     return ADERDG_OK;
@@ -319,10 +348,25 @@ aderdg_status aderdg_set_precision(aderdg_solver *s, int kernel, int prec) {
     if (!s) return ADERDG_E_INVALID;
     if (kernel < 0 || kernel > 3 || prec < 0 || prec > 3) FAIL(s, ADERDG_E_INVALID, "unknown kernel or precision");
     if (kernel == ADERDG_K_STORAGE) {
-        // the held state is rounded to the new storage precision
+        // the held state moves to a buffer of the new format, each value rounded
+        // to it (through FP64 staging)
+        const int old = storage(s);
+        if (prec == old) return ADERDG_OK;
+        void *nq = nullptr;
+        HIPC(s, hipStreamSynchronize(s->stream));
+        if (hipMalloc(&nq, (size_t)state_bytes(prec) * state_elems(s)) != hipSuccess)
+            FAIL(s, ADERDG_E_OOM, "state allocation failed");
+        convert_state(s, s->dQ, old, staging(s), ADERDG_FP64);
+        convert_state(s, staging(s), ADERDG_FP64, nq, prec);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) {
+            hipFree(nq);
+            FAIL(s, ADERDG_E_DEVICE, "state conversion: %s", hipGetErrorString(e));
+        }
+        hipFree(s->dQ);
+        s->dQ = nq;
         s->prec[kernel] = prec;
-        round_state(s);
-        HIPC(s, hipGetLastError());
         return ADERDG_OK;
     }
     if (kernel == ADERDG_K_PREDICTOR && !s->ks->pred[prec])
@@ -342,7 +386,7 @@ aderdg_status aderdg_max_dt(aderdg_solver *s, double cfl, double *dt_out) {
     if (!s || !dt_out) return ADERDG_E_INVALID;
     if (!(cfl > 0)) FAIL(s, ADERDG_E_INVALID, "cfl must be positive");
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, s->stream, s->dScalar, 0ull);
-    s->ks->maxeig(s->dQ, pde_args(s), s->ncell, s->dScalar, s->stream);
+    s->ks->maxeig(s->dQ, storage(s), pde_args(s), s->ncell, s->dScalar, s->stream);
     unsigned long long bits = 0;
     HIPC(s, hipMemcpyAsync(&bits, s->dScalar, sizeof(bits), hipMemcpyDeviceToHost, s->stream));
     HIPC(s, hipStreamSynchronize(s->stream));
@@ -546,16 +590,42 @@ aderdg_status aderdg_set_receivers(aderdg_solver *s, int nrec, const double *xyz
             for (int k = 0; k < s->n; k++)
                 phi[(size_t)r * 3 * kMaxN + i * kMaxN + k] = lagrange_value(s->n, s->hB.xi, k, loc[i]);
     }
+    // receivers grouped by cell: the adjoint scatter sums each cell's receivers
+    // in this fixed order
+    std::vector<int> order(nrec);
+    for (int r = 0; r < nrec; r++) order[r] = r;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cells[a] < cells[b]; });
+    std::vector<long> ucell;
+    std::vector<int> start;
+    for (int k = 0; k < nrec; k++) {
+        if (k == 0 || cells[order[k]] != cells[order[k - 1]]) {
+            ucell.push_back(cells[order[k]]);
+            start.push_back(k);
+        }
+    }
+    start.push_back(nrec);
     hipFree(s->dRecCell);
     hipFree(s->dRecPhi);
+    hipFree(s->dRecUcell);
+    hipFree(s->dRecStart);
+    hipFree(s->dRecOrder);
     s->dRecCell = nullptr;
     s->dRecPhi = nullptr;
+    s->dRecUcell = nullptr;
+    s->dRecStart = s->dRecOrder = nullptr;
     s->nrec = nrec;
+    s->nrec_cells = (int)ucell.size();
     if (nrec == 0) return ADERDG_OK;
     HIPC(s, hipMalloc(&s->dRecCell, sizeof(long) * nrec));
     HIPC(s, hipMalloc(&s->dRecPhi, sizeof(double) * phi.size()));
+    HIPC(s, hipMalloc(&s->dRecUcell, sizeof(long) * ucell.size()));
+    HIPC(s, hipMalloc(&s->dRecStart, sizeof(int) * start.size()));
+    HIPC(s, hipMalloc(&s->dRecOrder, sizeof(int) * nrec));
     HIPC(s, hipMemcpy(s->dRecCell, cells.data(), sizeof(long) * nrec, hipMemcpyHostToDevice));
     HIPC(s, hipMemcpy(s->dRecPhi, phi.data(), sizeof(double) * phi.size(), hipMemcpyHostToDevice));
+    HIPC(s, hipMemcpy(s->dRecUcell, ucell.data(), sizeof(long) * ucell.size(), hipMemcpyHostToDevice));
+    HIPC(s, hipMemcpy(s->dRecStart, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice));
+    HIPC(s, hipMemcpy(s->dRecOrder, order.data(), sizeof(int) * nrec, hipMemcpyHostToDevice));
     return ADERDG_OK;
 }
 
@@ -568,7 +638,8 @@ aderdg_status aderdg_read_receivers(aderdg_solver *s, double *out, int is_device
         HIPC(s, hipMalloc(&tmp, sizeof(double) * s->nrec));
         dst = tmp;
     }
-    hipLaunchKernelGGL(k_receivers, dim3((s->nrec + 63) / 64), dim3(64), 0, s->stream, s->dQ, s->V, s->S, s->n,
+    hipLaunchKernelGGL(k_receivers, dim3((s->nrec + 63) / 64), dim3(64), 0, s->stream, s->dQ, storage(s), s->V,
+                       s->S, s->n,
                        s->d, s->nrec, s->dRecCell, s->dRecPhi, dst);
     if (!is_device) {
         hipError_t e = hipMemcpyAsync(out, tmp, sizeof(double) * s->nrec, hipMemcpyDeviceToHost, s->stream);
@@ -650,7 +721,8 @@ aderdg_status aderdg_copy_faces(aderdg_solver *s, void *dst, int is_device) {
 aderdg_status aderdg_receivers_adjoint(aderdg_solver *s, const double *weight_dev, double *lam_dev) {
     if (!s || !weight_dev || !lam_dev) return ADERDG_E_INVALID;
     if (s->nrec == 0) return ADERDG_OK;
-    receivers_adjoint(lam_dev, s->V, s->S, s->n, s->d, s->nrec, s->dRecCell, s->dRecPhi, weight_dev, s->stream);
+    receivers_adjoint(lam_dev, s->V, s->S, s->n, s->d, s->nrec_cells, s->dRecUcell, s->dRecStart, s->dRecOrder,
+                      s->dRecPhi, weight_dev, s->stream);
     HIPC(s, hipGetLastError());
     return ADERDG_OK;
 }
@@ -677,7 +749,8 @@ aderdg_status aderdg_info(const aderdg_solver *s, long long *info) {
 
 aderdg_status aderdg_state_ptr(aderdg_solver *s, double **dev_ptr) {
     if (!s || !dev_ptr) return ADERDG_E_INVALID;
-    *dev_ptr = s->dQ;
+    if (storage(s) != ADERDG_FP64) FAIL(s, ADERDG_E_UNSUPPORTED, "the state is held in a narrower format");
+    *dev_ptr = (double *)s->dQ;
     return ADERDG_OK;
 }
 

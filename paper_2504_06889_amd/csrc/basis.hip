@@ -1,5 +1,5 @@
 // Host construction of the nodal basis and the ADER-DG operators in FP64
-// (arXiv 2504.06889, Sec. 2), plus their roundings to each contraction format.
+// (arXiv 2504.06889, Sec. 3), plus their roundings to each contraction format.
 //
 //  - Gauss-Legendre nodes/weights on [0,1] from the eigen-decomposition of the
 //    Legendre Jacobi matrix (Golub-Welsch), by cyclic Jacobi rotations.

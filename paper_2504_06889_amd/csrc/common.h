@@ -1,6 +1,6 @@
 // Device-side building blocks of the ADER-DG step for gfx950 (MI355X):
 // compile-time shapes, precision conversions, basis constants and the PDE
-// systems of arXiv 2504.06889, Sec. 4.
+// systems of arXiv 2504.06889, Sec. 5.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -75,9 +75,9 @@ __device__ __forceinline__ float widen(__hip_bfloat16 x) { return __bfloat162flo
 __device__ __forceinline__ float widen(_Float16 x) { return (float)x; }
 __device__ __forceinline__ double widen(double x) { return x; }
 
-// Storage precision of the persistent state (Prec SP): the state is held in
-// FP64 containers, each value rounded to the format (FP32 first, then the
-// format, nearest-even) whenever it is stored between traversals.
+// Storage precision of the persistent state (Prec SP): each value is rounded
+// to the format (FP32 first, then the format, nearest-even) whenever it is
+// stored between traversals.
 __device__ __forceinline__ double round_q(double x, int sp) {
     if (sp == P64) return x;
     const float f = (float)x;
@@ -85,6 +85,27 @@ __device__ __forceinline__ double round_q(double x, int sp) {
     if (sp == PBF16) return (double)widen(round_to<PBF16>(f));
     return (double)widen(round_to<PF16>(f));
 }
+
+// The persistent state in HBM, element type by storage precision SP: FP64, or
+// FP32/BF16/FP16 holding the value rounded as above.  Loads widen exactly to
+// FP64 (all arithmetic stays FP64); stores round.  SP is uniform per launch.
+__device__ __forceinline__ double load_state(const void *Q, long i, int sp) {
+    if (sp == P64) return static_cast<const double *>(Q)[i];
+    if (sp == P32) return (double)static_cast<const float *>(Q)[i];
+    if (sp == PBF16) return (double)widen(static_cast<const __hip_bfloat16 *>(Q)[i]);
+    return (double)widen(static_cast<const _Float16 *>(Q)[i]);
+}
+__device__ __forceinline__ void store_state(void *Q, long i, double x, int sp) {
+    if (sp == P64) {
+        static_cast<double *>(Q)[i] = x;
+        return;
+    }
+    const float f = (float)x;
+    if (sp == P32) static_cast<float *>(Q)[i] = f;
+    else if (sp == PBF16) static_cast<__hip_bfloat16 *>(Q)[i] = round_to<PBF16>(f);
+    else static_cast<_Float16 *>(Q)[i] = round_to<PF16>(f);
+}
+__host__ __device__ constexpr int state_bytes(int sp) { return sp == P64 ? 8 : (sp == P32 ? 4 : 2); }
 
 // Face-value storage per FLUX precision
 template <int P> struct FaceT { using T = typename Store<P>::T; };

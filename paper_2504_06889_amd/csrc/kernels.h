@@ -28,7 +28,7 @@
 namespace aderdg {
 
 struct StepArgs {
-    double *Q;            // state [ncell][V][S]
+    void *Q;              // state [ncell][V][S] in the storage precision store_prec
     void *faces;          // face buffer written by the predictor
     const void *faces_in; // fused step: the previous step's face buffer (corrector input)
     const DevBasis *B;
@@ -40,7 +40,7 @@ struct StepArgs {
     int iters;            // Picard iterations
     int write_state;      // 0: only the face data is produced (Q untouched)
     int ck;               // 1: Cauchy-Kowalevskaya predictor (linear PDEs, no source)
-    int store_prec;       // storage precision of Q (Prec): stored values are rounded to it
+    int store_prec;       // storage precision of Q (Prec): its element type; stored values are rounded to it
     long src_cell;        // -1: no source
     const double *src_phi;
     // point source: h s(t + xi_b dt) at the n time nodes and the time average
@@ -133,8 +133,8 @@ __device__ __forceinline__ uint32_t pack2(float lo, float hi) {
 // position, variable)); the constant A operand holds D on the interleaved
 // block diagonal (row (line pair, i, var), column (line pair, k, var)), so a
 // C column is the derivative of both variables of its line pairs.  FP32
-// results go to Y[LP*(2*NPOS + 2) + 2*i + var] (the padded line-pair stride
-// puts the 16 lanes of a 64-bit store on distinct banks).  Lane layouts (64 lanes,
+// results go to Y[LP*OSTRIDE + 2*i + var] (ostride() below; in FP32 the
+// padding positions are not stored).  Lane layouts (64 lanes,
 // 16x16xK): A[row = lane%16][k], B[k][col = lane%16],
 // C[row = 4*(lane/16) + e][col], with lane group g = lane/16 holding
 // k = 4g..4g+3 (16-bit formats), or one k per instruction ordered so that its
@@ -147,10 +147,18 @@ struct PairGeom {
     static constexpr int LPC = 8 / NPOS;   // line pairs per tile column
     static constexpr int PPL = NPOS / 2;   // position pairs per line
     static constexpr int LSTRIDE = 2 * NPOS;      // input elements per line pair
-    static constexpr int OSTRIDE = 2 * NPOS + 2;  // output floats per line pair
+    // output floats per line pair, an odd number of float pairs (the 16 lanes
+    // of a 64-bit store then cover the 32 banks once): all NPOS positions of
+    // both variables, or, in FP32 (whose larger operands would otherwise keep
+    // a third workgroup out of a CU's LDS), only the n real positions, the
+    // padding rows not stored.  Measured: trimming the 16-bit formats' rows
+    // costs 10 % (3-D elastic N=5) although it saves LDS traffic.
+    template <int P>
+    static constexpr int ostride() { return P == P32 ? 2 * ((n + 1) | 1) : 2 * NPOS + 2; }
     __device__ static constexpr int sw(int f) { return (f >> 2) & (PPL - 1); }
     __device__ static int in_off(int lp, int f, int k) { return lp * LSTRIDE + 4 * ((k >> 1) ^ sw(f)) + 2 * (k & 1); }
-    __device__ static int out_off(int lp, int k) { return lp * OSTRIDE + 2 * k; }
+    template <int P>
+    __device__ static int out_off(int lp, int k) { return lp * ostride<P>() + 2 * k; }
 };
 
 template <int P, int n>
@@ -226,9 +234,9 @@ struct MfmaPairs {
             for (int k = 0; k < TB; k++) {
                 const int tile = wave + (k0 + k) * NWAVE;
                 if (k0 + k < TPW && tile < NTILE) {
-                    float *y = Y + lp[k] * G::OSTRIDE + 4 * gp;
-                    *reinterpret_cast<f32x2 *>(y) = f32x2{cc[k][0], cc[k][1]};
-                    *reinterpret_cast<f32x2 *>(y + 2) = f32x2{cc[k][2], cc[k][3]};
+                    float *y = Y + lp[k] * G::template ostride<P>() + 4 * gp;
+                    if (P != P32 || 2 * gp < n) *reinterpret_cast<f32x2 *>(y) = f32x2{cc[k][0], cc[k][1]};
+                    if (P != P32 || 2 * gp + 1 < n) *reinterpret_cast<f32x2 *>(y + 2) = f32x2{cc[k][2], cc[k][3]};
                 }
             }
         }
@@ -383,10 +391,10 @@ struct PicardLayout {
     static constexpr int NLPR = CPB * DIM * NP * F;
     static constexpr int NTILE = (NLPR + 16 * G::LPC - 1) / (16 * G::LPC);
     static constexpr int PSTRIDE = G::LSTRIDE * F;   // input elements between variable pairs
-    static constexpr int POSTRIDE = G::OSTRIDE * F;  // output floats between variable pairs
+    static constexpr int POSTRIDE = G::template ostride<PP>() * F;  // output floats between variable pairs
     static constexpr size_t esz = PP == P64 ? 8 : sizeof(typename Store<PP>::T);
     static constexpr size_t in_bytes = (size_t)NTILE * 16 * 16 * esz;
-    static constexpr size_t out_bytes = (size_t)NTILE * 16 * G::LPC * G::OSTRIDE * 4;
+    static constexpr size_t out_bytes = (size_t)NTILE * 16 * G::LPC * G::template ostride<PP>() * 4;
     static constexpr size_t bytes = PP == P64 ? (size_t)n * NLP * 8 : in_bytes + out_bytes;
 };
 
@@ -492,7 +500,7 @@ __device__ __forceinline__ void correct_block(const StepArgs &a, const void *fac
     const bool active = cb < CPB && cell < a.ncell;
     double qs[V];
 #pragma unroll
-    for (int v = 0; v < V; v++) qs[v] = active ? a.Q[(cell * V + v) * S + s] : 1.0;
+    for (int v = 0; v < V; v++) qs[v] = active ? load_state(a.Q, (cell * V + v) * S + s, a.store_prec) : 1.0;
 
     constexpr int NRI = CPB * DIM * 2 * F;
     for (int itm = tid; itm < NRI; itm += TPB) {
@@ -565,7 +573,8 @@ __device__ __forceinline__ void correct_block(const StepArgs &a, const void *fac
                 }
             }
         }
-        // the corrected state as stored in the storage precision
+        // the corrected state as held in the storage precision (the fused kernel
+        // keeps it in registers as the next step's state)
         qnew[v] = active ? round_q(fma(a.sigma, dq, qs[v]), a.store_prec) : 1.0;
     }
 }
@@ -587,7 +596,7 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) void k_corrector(StepArgs a) 
     const int cb = tid / S, s = tid % S;
     const long cell = cell0 + cb;
     if (cb < CPB && cell < a.ncell) {
-        for (int v = 0; v < V; v++) a.Q[(cell * V + v) * S + s] = qnew[v];
+        for (int v = 0; v < V; v++) store_state(a.Q, (cell * V + v) * S + s, qnew[v], a.store_prec);
     }
 }
 
@@ -628,7 +637,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         __syncthreads();  // the LDS is reused below
     } else {
 #pragma unroll
-        for (int v = 0; v < V; v++) Qn[v] = active ? a.Q[(cell * V + v) * S + s] : 1.0;
+        for (int v = 0; v < V; v++) Qn[v] = active ? load_state(a.Q, (cell * V + v) * S + s, a.store_prec) : 1.0;
     }
 
     // volume term of the node (sum over directions of Kxi along fbar_j)
@@ -828,7 +837,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         for (int j = 0; j < DIM; j++) {
             const int f = face_of<n, DIM>(s, j), k = coord<n>(s, j);
             io[j] = PL::G::in_off(po[j], f, k);
-            oo[j] = PL::G::out_off(po[j], k);
+            oo[j] = PL::G::template out_off<PP>(po[j], k);
         }
         __syncthreads();
         // One contraction pass on the matrix cores: the owners write the flux
@@ -837,75 +846,81 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         // node's results over the directions in FP32: sink(rf, eta) with rf[v]
         // the sum for variable v and eta[j] the derivative of the
         // non-conservative input along j.
-        auto pass = [&](const MfmaPairs<PP, n> &M, auto &&flux_j, auto &&sink) __attribute__((always_inline)) {
-            if (slot) {
+        auto write_flux = [&](T *FbB, auto &&flux_j) __attribute__((always_inline)) {
 #pragma unroll
-                for (int j = 0; j < DIM; j++) {
-                    float Fv[V], ev;
-                    flux_j(j, Fv, ev);
-                    auto comp_val = [&](int c) -> float { return c < 0 ? 0.0f : (c == V ? ev : Fv[c < V ? c : 0]); };
+            for (int j = 0; j < DIM; j++) {
+                float Fv[V], ev;
+                flux_j(j, Fv, ev);
+                auto comp_val = [&](int c) -> float { return c < 0 ? 0.0f : (c == V ? ev : Fv[c < V ? c : 0]); };
 #pragma unroll
-                    for (int p = 0; p < PL::NP; p++) {
-                        T *dst = Fb + io[j] + p * PL::PSTRIDE;
-                        const float f0 = comp_val(PL::FS::comp(j, 2 * p)), f1 = comp_val(PL::FS::comp(j, 2 * p + 1));
-                        if constexpr (PP == P32) *reinterpret_cast<f32x2 *>(dst) = f32x2{f0, f1};
-                        else *reinterpret_cast<uint32_t *>(dst) = pack2<PP>(f0, f1);
+                for (int p = 0; p < PL::NP; p++) {
+                    T *dst = FbB + io[j] + p * PL::PSTRIDE;
+                    const float f0 = comp_val(PL::FS::comp(j, 2 * p)), f1 = comp_val(PL::FS::comp(j, 2 * p + 1));
+                    if constexpr (PP == P32) *reinterpret_cast<f32x2 *>(dst) = f32x2{f0, f1};
+                    else *reinterpret_cast<uint32_t *>(dst) = pack2<PP>(f0, f1);
+                }
+            }
+        };
+        auto gather = [&](const float *RbB, auto &&sink) __attribute__((always_inline)) {
+            float rf[V], eta[DIM];
+#pragma unroll
+            for (int v = 0; v < V; v++) rf[v] = 0.0f;
+#pragma unroll
+            for (int j = 0; j < DIM; j++) {
+#pragma unroll
+                for (int p = 0; p < PL::NP; p++) {
+                    const f32x2 r2 = *reinterpret_cast<const f32x2 *>(RbB + oo[j] + p * PL::POSTRIDE);
+#pragma unroll
+                    for (int h = 0; h < 2; h++) {
+                        const int c = PL::FS::comp(j, 2 * p + h);
+                        if (c >= 0 && c < V) {
+                            if (PL::FS::first(j, c)) rf[c < V ? c : 0] = r2[h];
+                            else rf[c < V ? c : 0] += r2[h];
+                        }
+                        if (Pde::kNCP && c == V) eta[j] = r2[h];
                     }
                 }
             }
+            if (active) sink(rf, eta);
+        };
+        auto pass = [&](const MfmaPairs<PP, n> &M, auto &&flux_j, auto &&sink) __attribute__((always_inline)) {
+            if (slot) write_flux(Fb, flux_j);
             __syncthreads();
             M.template run<PL::NTILE, NWAVE, F>(Fb, Rb, wave, lane);
             __syncthreads();
             // every slot thread reads its results, so this block and the next
             // slice's flux writes share one condition; only real cells fold them
-            if (slot) {
-                float rf[V], eta[DIM];
-#pragma unroll
-                for (int v = 0; v < V; v++) rf[v] = 0.0f;
-#pragma unroll
-                for (int j = 0; j < DIM; j++) {
-#pragma unroll
-                    for (int p = 0; p < PL::NP; p++) {
-                        const f32x2 r2 = *reinterpret_cast<const f32x2 *>(Rb + oo[j] + p * PL::POSTRIDE);
-#pragma unroll
-                        for (int h = 0; h < 2; h++) {
-                            const int c = PL::FS::comp(j, 2 * p + h);
-                            if (c >= 0 && c < V) {
-                                if (PL::FS::first(j, c)) rf[c < V ? c : 0] = r2[h];
-                                else rf[c < V ? c : 0] += r2[h];
-                            }
-                            if (Pde::kNCP && c == V) eta[j] = r2[h];
-                        }
-                    }
-                }
-                if (active) sink(rf, eta);
-            }
+            if (slot) gather(Rb, sink);
         };
         // One slice: flux of q_b at every node, the derivative lines and the
         // divergence at the node, whose FP64 value for variable v goes to
         // sink(v, r) (descending v).  The flux sees the FP32 rounding of the
         // FP64 iterate (exact when FR).
+        auto slice_flux = [&](const float *qb) __attribute__((always_inline)) {
+            return [&, qb](int j, float *Fv, float &ev) __attribute__((always_inline)) {
+                Pde::flux(coef, qb, j, Fv);
+                ev = ncp_value<Pde>(qb);
+            };
+        };
+        auto slice_sink = [&](const float *qb, auto &&sink) __attribute__((always_inline)) {
+            return [&, qb](const float *rf, const float *eta) __attribute__((always_inline)) {
+#pragma unroll
+                for (int v = V - 1; v >= 0; v--) {
+                    double rr = (double)rf[v];
+                    if constexpr (Pde::kNCP) {
+                        if (v >= 1 && v <= DIM) rr += (double)((float)coef.g * qb[0] * eta[v - 1]);
+                    }
+                    sink(v, rr);
+                }
+            };
+        };
         auto slice = [&](int b, auto &&sink) __attribute__((always_inline)) {
             float qb[V];
 #pragma unroll
             for (int v = 0; v < V; v++) qb[v] = (float)z[b][v];
-            pass(
-                mp,
-                [&](int j, float *Fv, float &ev) __attribute__((always_inline)) {
-                    Pde::flux(coef, qb, j, Fv);
-                    ev = ncp_value<Pde>(qb);
-                },
-                [&](const float *rf, const float *eta) __attribute__((always_inline)) {
-#pragma unroll
-                    for (int v = V - 1; v >= 0; v--) {
-                        double rr = (double)rf[v];
-                        if constexpr (Pde::kNCP) {
-                            if (v >= 1 && v <= DIM) rr += (double)((float)coef.g * qb[0] * eta[v - 1]);
-                        }
-                        sink(v, rr);
-                    }
-                });
+            pass(mp, slice_flux(qb), slice_sink(qb, sink));
         };
+
         // The first and the last iteration are peeled off the loop, so that
         // qbar, formed with the last iterate, is not carried through it.
         if (ck) {
@@ -932,7 +947,8 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
 #pragma unroll 1
             for (int it = 1; it < iters; it++) {
 #pragma unroll
-                for (int b = 0; b < n; b++) slice(b, [&](int v, double r) __attribute__((always_inline)) { fold(it, b, v, r, false); });
+                for (int b = 0; b < n; b++)
+                    slice(b, [&](int v, double r) __attribute__((always_inline)) { fold(it, b, v, r, false); });
                 if (it < iters - 1 && active) update(false);
             }
             if (active) update(true);
@@ -1141,7 +1157,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
             double qn = Qn[v] + a.sigma * vol[v];
             if constexpr (Pde::kNCP) qn -= a.sigma * nbar[v];
             if (v == 0 && src_here) qn += a.dt * sbar * src_phi;
-            a.Q[(cell * V + v) * S + s] = round_q(qn, a.store_prec);  // Q* in the storage precision
+            store_state(a.Q, (cell * V + v) * S + s, qn, a.store_prec);  // Q* in the storage precision
         }
     }
 }
@@ -1152,7 +1168,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
 // 64-bit pattern gives the maximum.
 // ---------------------------------------------------------------------------
 template <class Pde, int DIM, int N>
-__global__ __launch_bounds__(256) void k_maxeig(const double *Q, PdeArgs pde, long ncell,
+__global__ __launch_bounds__(256) void k_maxeig(const void *Q, int sp, PdeArgs pde, long ncell,
                                                 unsigned long long *out) {
     using Sh = Shape<DIM, N>;
     constexpr int S = Sh::S, V = Pde::V;
@@ -1164,7 +1180,7 @@ __global__ __launch_bounds__(256) void k_maxeig(const double *Q, PdeArgs pde, lo
         const int s = i % S;
         double q[V];
 #pragma unroll
-        for (int v = 0; v < V; v++) q[v] = Q[(c * V + v) * S + s];
+        for (int v = 0; v < V; v++) q[v] = load_state(Q, (c * V + v) * S + s, sp);
         const typename Pde::Coef k = Pde::cell(pde, c);
 #pragma unroll
         for (int j = 0; j < DIM; j++) {

@@ -5,7 +5,7 @@
 namespace aderdg {
 
 using StepFn = void (*)(const StepArgs &, hipStream_t);
-using MaxEigFn = void (*)(const double *, const PdeArgs &, long, unsigned long long *, hipStream_t);
+using MaxEigFn = void (*)(const void *, int, const PdeArgs &, long, unsigned long long *, hipStream_t);
 
 struct KernelSet {
     StepFn pred[4] = {nullptr, nullptr, nullptr, nullptr};  // by predictor precision
@@ -34,11 +34,12 @@ struct Instance {
     static void corr(const StepArgs &a, hipStream_t st) {
         hipLaunchKernelGGL((k_corrector<Pde, DIM, N, FP>), dim3(grid(a.ncell)), dim3(Sh::TPB), 0, st, a);
     }
-    static void maxeig(const double *Q, const PdeArgs &p, long ncell, unsigned long long *out, hipStream_t st) {
+    static void maxeig(const void *Q, int sp, const PdeArgs &p, long ncell, unsigned long long *out,
+                       hipStream_t st) {
         long total = ncell * Sh::S;
         long g = (total + 255) / 256;
         if (g > 4096) g = 4096;
-        hipLaunchKernelGGL((k_maxeig<Pde, DIM, N>), dim3(g), dim3(256), 0, st, Q, p, ncell, out);
+        hipLaunchKernelGGL((k_maxeig<Pde, DIM, N>), dim3(g), dim3(256), 0, st, Q, sp, p, ncell, out);
     }
     Instance(int pde, bool mixed) {
         KernelSet ks;

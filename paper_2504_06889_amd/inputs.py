@@ -6,15 +6,15 @@ supplies, draws the seeded per-cell material and receiver positions, and
 names the five benchmark configurations.  Both the GPU path and the CPU
 oracle take their inputs from here.
 
-Scenarios (arXiv 2504.06889, Sec. 4):
+Scenarios (arXiv 2504.06889, Sec. 5):
   planar waves  Q = omega sin(omega t - k.x) q0 with (omega, q0) an eigenpair
                 of sum_j k_j A_j (Sec. 5.2, planar waves), acoustic and elastic,
                 and 3-D elastic P and S plane waves along an oblique k;
   Euler         advected density sine wave (exact: shifted initial state), the
-                smooth Gaussian bell (Sec. 4.3.1, exp(-50 r^2) reading) and the
-                static isentropic vortex (Sec. 4.3.2, with p = (1+dT)^(g/(g-1))
+                smooth Gaussian bell (Sec. 5.3.1, exp(-50 r^2) reading) and the
+                static isentropic vortex (Sec. 5.3.2, with p = (1+dT)^(g/(g-1))
                 and v_inf + dv, the reading that keeps p / rho^g = 1);
-  shallow water lake at rest (Sec. 4.4.1) and a bump with a small sine
+  shallow water lake at rest (Sec. 5.4.1) and a bump with a small sine
                 perturbation of the surface.
 """
 import math
@@ -54,7 +54,7 @@ def _pack(fields, coords):
 
 
 # --------------------------------------------------------------------------
-# Planar waves (Sec. 4.2.1)
+# Planar waves (Sec. 5.2.1)
 # --------------------------------------------------------------------------
 
 def acoustic_eigvec(k, K, rho):
@@ -154,7 +154,7 @@ def planar_elastic_oblique(coords, t, rho, lam, mu, k=(2 * math.pi,) * 3, amp_p=
 
 
 # --------------------------------------------------------------------------
-# Euler (Sec. 4.3)
+# Euler (Sec. 5.3)
 # --------------------------------------------------------------------------
 
 def euler_density_wave(coords, t, gamma, amp=0.2, u=1.0, p=1.0):
@@ -194,7 +194,7 @@ def euler_vortex(coords, gamma, beta=5.0):
 
 
 # --------------------------------------------------------------------------
-# Shallow water (Sec. 4.4)
+# Shallow water (Sec. 5.4)
 # --------------------------------------------------------------------------
 
 def swe_lake_at_rest(coords, eta0=2.0):
@@ -316,18 +316,18 @@ SCENARIOS = {
          "checkpoint": 20, "c_mean": 1.5, "c_sigma": 0.2, "seed_c": 0, "seed_rec": 1}),
 }
 
-# The paper's 2-D scenarios of its mixed-precision study (Sec. 4, Sec. 5.4): 27^2 cells,
+# The paper's 2-D scenarios of its mixed-precision study (Sec. 5, Sec. 7): 27^2 cells,
 # order 5, periodic.  Each runs to extra["t_end"] (steps = 0: the step count follows from
 # dt = C h / (d (2N+1) lambda_max) of the initial state); extra["exact"] says whether the
 # scenario has a closed-form solution at t_end.
-#  - acoustic planar wave (Sec. 4.2.1): [-1,1]^2, K = 4, rho = 1 (c = 2), wave along the
+#  - acoustic planar wave (Sec. 5.2.1): [-1,1]^2, K = 4, rho = 1 (c = 2), wave along the
 #    diagonal, k = (pi, pi): the state returns to the initial one at t = sqrt(2) (t_end);
-#  - elastic planar waves (Sec. 4.2.1): [-1,1]^2, lambda = 2, mu = 1, rho = 1 (cp = 2,
+#  - elastic planar waves (Sec. 5.2.1): [-1,1]^2, lambda = 2, mu = 1, rho = 1 (cp = 2,
 #    cs = 1), P wave along x (k = pi) and S wave along y (k = 2 pi), both of period 1 (t_end);
-#  - Euler Gaussian bell (Sec. 4.3.1): rho = 0.02 (1 + exp(-50 r^2)), v = (1, 1), p = 1 on
+#  - Euler Gaussian bell (Sec. 5.3.1): rho = 0.02 (1 + exp(-50 r^2)), v = (1, 1), p = 1 on
 #    [-1,1]^2, t_end = 2 (one period of the advection);
-#  - static isentropic vortex (Sec. 4.3.2): beta = 5 on [-5,5]^2, t_end = 10;
-#  - lake at rest (Sec. 4.4.1): b = sin(2 pi (x + y)), h = eta0 - b, eta0 = 2, g = 9.81 on
+#  - static isentropic vortex (Sec. 5.3.2): beta = 5 on [-5,5]^2, t_end = 10;
+#  - lake at rest (Sec. 5.4.1): b = sin(2 pi (x + y)), h = eta0 - b, eta0 = 2, g = 9.81 on
 #    [-1,1]^2, t_end = 1.
 PAPER_SUITE = {
     "acoustic2d_n5_27_planar": Scenario(

@@ -48,3 +48,52 @@ def test_lower_format_contractions(oracle_mod, name, p):
     assert r < 10 * r_emu + 1e-12
     if p in ("bf16", "fp16"):
         assert r_ge < 0.5 * r_emu
+
+
+# the settings of the paper's FP32-storage table and its table of one kernel in
+# FP64 on a lower base, as (predictor, volume, flux, storage)
+TABLE_CASES = [("storage32:Picard=bf16", ("bf16", "fp32", "fp32", "fp32")),
+               ("storage32:predictor=fp16", ("fp16", "fp16", "fp32", "fp32")),
+               ("storage32:corrector=bf16", ("fp32", "fp32", "bf16", "fp32")),
+               ("base16:reference", ("fp16",) * 4),
+               ("base16:predictor=fp64", ("fp64", "fp64", "fp16", "fp16")),
+               ("base32:corrector=fp64", ("fp32", "fp32", "fp64", "fp32")),
+               ("basebf16:all=fp64", ("fp64", "fp64", "fp64", "bf16"))]
+
+
+@pytest.mark.parametrize("name", ["acoustic2d_n5_27_planar", "euler2d_n5_27_bell"])
+@pytest.mark.parametrize("label,prec", TABLE_CASES)
+def test_table_settings_match_emulation(oracle_mod, name, label, prec):
+    """The GPU's side of the paper-table runs (each kernel's contractions and the
+    stored state in the setting's formats, 3 steps on the 27^2 grid) against the
+    oracle's emulation of the same rounding points.  With a 16-bit format in the
+    setting, its rounding dominates and the GPU is far closer to the emulation than
+    to FP64; with FP32 the lowest format, the two sides' different FP32
+    accumulation orders are of the same size as the FP32 rounding itself, so the
+    GPU is held to the FP32 tolerance against FP64 and to the emulation's level."""
+    sc = inputs.PAPER_SUITE[name]
+    print("case", name, label, flush=True)
+    ref = make_oracle(oracle_mod, sc, sc.cells)
+    Q0 = sc.initial_state(ref.node_coords())
+    ref.set_state(Q0)
+    dt = ref.max_dt(sc.cfl)
+    A = ref.run(3, dt)
+    emu = oracle_mod.Oracle(sc.dim, sc.order, sc.cells, sc.lo, sc.hi, sc.pde, sc.params, prec=prec[:3],
+                            storage=prec[3])
+    emu.set_state(Q0)
+    E = emu.run(3, dt)
+    from _util import gpu_solver
+    g = gpu_solver(sc, sc.cells, prec=prec[:3])
+    g.set_precision("storage", prec[3])
+    g.set_state(Q0)
+    g.step(dt, 3)
+    B = g.get_state()
+    assert np.all(np.isfinite(B))
+    r_emu, r_ge, r = rel_l2(ref, E, A), rel_l2(ref, B, E), rel_l2(ref, B, A)
+    print("levels", name, label, "gpu-vs-fp64 %.3e emu-vs-fp64 %.3e gpu-vs-emu %.3e" % (r, r_emu, r_ge),
+          flush=True)
+    assert r_emu > 0
+    if any(p in ("bf16", "fp16") for p in prec):
+        assert r_ge < 0.5 * r_emu
+    else:
+        assert r <= 1e-6 and r_ge <= 2 * r_emu

@@ -126,3 +126,30 @@ def test_adjoint_refused_with_lower_storage():
     with pytest.raises(AderdgError) as e:
         g.step_adjoint(1e-3, 0.0, Qn, lam, grad)
     assert e.value.code == -2
+
+
+@pytest.mark.parametrize("sp,nbytes", [("fp32", 4), ("bf16", 2), ("fp16", 2)])
+def test_storage_state_is_narrow_in_device_memory(sp, nbytes):
+    """The state buffer is reallocated in the storage format: the device memory
+    it frees is the difference of the element sizes (4-byte or 2-byte elements
+    instead of 8), and the raw FP64 pointer is refused while it is narrow."""
+    import torch
+    import ctypes
+
+    from paper_2504_06889_amd.aderdg import lib
+    sc = _grid("elastic", 3, 5, (16, 16, 16), (2.7, 32.4, 32.398), "planar_elastic", {"kP": TWO_PI, "kS": TWO_PI})
+    g = gpu_solver(sc, sc.cells, prec=CASES["elastic3d_n5"][1])
+    state_bytes = g.ncell * g.V * g.S * 8
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    g.set_precision("storage", sp)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    saved = free1 - free0
+    expect = state_bytes * (8 - nbytes) // 8
+    print("storage", sp, "freed", saved, "expected", expect, flush=True)
+    assert abs(saved - expect) <= 0.05 * state_bytes, (saved, expect)
+    p = ctypes.c_void_p()
+    assert lib().aderdg_state_ptr(g._h, ctypes.byref(p)) == -2
+    g.set_precision("storage", "fp64")
+    assert lib().aderdg_state_ptr(g._h, ctypes.byref(p)) == 0

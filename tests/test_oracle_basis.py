@@ -1,5 +1,5 @@
 """Pins of the oracle's basis and operators against closed forms, library routines
-and identities (arXiv 2504.06889, Sec. 2: Gauss-Legendre support points,
+and identities (arXiv 2504.06889, Sec. 3: Gauss-Legendre support points,
 eq. Picard time matrix, eq. weak_form_volume_surface volume and face terms)."""
 import math
 
@@ -111,7 +111,7 @@ def test_rounding_matches_library_conversions(oracle_mod):
 
 
 def test_cast_error_ratios_follow_mantissa_bits(oracle_mod):
-    """Initial-error ratios of Sec. 5.1: fp16/fp32 ~ 2^13 and bf16/fp16 ~ 2^3."""
+    """Initial-error ratios of Sec. 6.1: fp16/fp32 ~ 2^13 and bf16/fp16 ~ 2^3."""
     rng = np.random.default_rng(3)
     x = rng.uniform(-1, 1, 4000)
     err = {}

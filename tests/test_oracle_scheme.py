@@ -1,4 +1,4 @@
-"""Pins of the oracle's full ADER-DG step (arXiv 2504.06889, Sec. 2, Alg. 1)
+"""Pins of the oracle's full ADER-DG step (arXiv 2504.06889, Sec. 3, Alg. 1)
 against brute-force solves, closed forms, reductions to textbook schemes,
 exact solutions and invariants."""
 import math
@@ -288,7 +288,7 @@ def test_acoustic_energy_does_not_grow(oracle_mod):
 
 
 def test_lake_at_rest_is_preserved(oracle_mod):
-    """Well-balancedness (Sec. 4.4.1): eta = h + b = 2 and zero velocity stay so up
+    """Well-balancedness (Sec. 5.4.1): eta = h + b = 2 and zero velocity stay so up
     to rounding in FP64."""
     sc = small("swe", 2, 4, (5, 5), (0, 0), (1, 1), (9.81,), "swe_lake", {"eta0": 2.0}, cfl=0.45)
     o = make_oracle(oracle_mod, sc)

@@ -1,5 +1,5 @@
 """Pins of the oracle's storage precision (the persistent state held in FP32, BF16 or
-FP16 between traversals, Sec. 3.1): FP64 storage is the plain step; every stored
+FP16 between traversals, Sec. 4.1): FP64 storage is the plain step; every stored
 value is representable in the format; at N = 0 a step is the textbook Rusanov
 finite-volume update rounded to the format (independent code and rounding); the
 difference to FP64 storage stays at the level of the format's spacing."""
