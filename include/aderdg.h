@@ -190,6 +190,22 @@ aderdg_status aderdg_copy_faces(aderdg_solver *s, void *dst, int is_device);
 aderdg_status aderdg_step_adjoint_faces(aderdg_solver *s, double dt, double t, const double *Qn_dev,
                                         const void *fwd_faces_dev, double *lam_dev, double *grad_dev);
 
+/* aderdg_step_adjoint_faces for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments and results, bit for bit, but the face
+ * restrictions of the incoming adjoint go to a static device array of the
+ * library (ADERDG_NOALLOC_SCRATCH_BYTES = 64 MiB on each GPU the library runs
+ * on, held until the process ends) and no device memory is allocated or freed.
+ * Limit: ncell * dim * 2 * (dim + 1) * (order + 1)^(dim - 1) * 8 bytes must not
+ * exceed the array (e.g. 9709 cells of 3-D order 5).  Every call on one GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (several
+ * streams or threads) race and must be serialised by the caller.
+ * Errors: INVALID (null pointer, dt <= 0, grid beyond the limit), the other
+ * errors of aderdg_step_adjoint.                                              */
+#define ADERDG_NOALLOC_SCRATCH_BYTES (64u << 20)
+aderdg_status aderdg_step_adjoint_faces_noalloc(aderdg_solver *s, double dt, double t, const double *Qn_dev,
+                                                const void *fwd_faces_dev, double *lam_dev, double *grad_dev);
+
 /* Scatter the receiver misfit gradient (the transpose of the receiver
  * read-out): lam[cell][0][node] += sum_r weight[r] * phi_node(x_r) over the
  * receivers in that cell (device pointers: weight[nrec], lam in the state

@@ -41,7 +41,7 @@ EXPORTS = [
     "aderdg_set_source", "aderdg_set_receivers", "aderdg_read_receivers", "aderdg_step_adjoint",
     "aderdg_receivers_adjoint", "aderdg_nodes", "aderdg_info", "aderdg_state_ptr", "aderdg_last_error",
     "aderdg_set_timing", "aderdg_get_timing", "aderdg_copy_faces", "aderdg_step_adjoint_faces",
-    "aderdg_set_predictor",
+    "aderdg_set_predictor", "aderdg_step_adjoint_faces_noalloc",
 ]
 PREDICTORS = {"picard": 0, "ck": 1}
 
@@ -82,6 +82,7 @@ def lib():
         "aderdg_copy_faces": [vp, vp, i],
         "aderdg_step_adjoint_faces": [vp, d, d, vp, vp, vp, vp],
         "aderdg_set_predictor": [vp, i],
+        "aderdg_step_adjoint_faces_noalloc": [vp, d, d, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -336,6 +337,18 @@ class Solver:
             self._check(lib().aderdg_step_adjoint_faces(
                 self._h, float(dt), float(t), ctypes.c_void_p(Qn.data_ptr()), ctypes.c_void_p(fwd_faces.data_ptr()),
                 ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(grad.data_ptr())))
+
+    def step_adjoint_noalloc(self, dt, t, Qn, lam, grad, fwd_faces):
+        """step_adjoint with the forward face data given, through the entry point that
+        allocates no device memory (the library's static scratch array; small grids)."""
+        check_tensors([(Qn, "Qn", self._state_numel()), (lam, "lam", self._state_numel()),
+                       (grad, "grad", self.ncell), (fwd_faces, "fwd_faces", fwd_faces.numel(), "uint8")],
+                      self.device)
+        if fwd_faces.numel() < self.face_bytes():
+            raise ValueError("fwd_faces must hold at least %d bytes" % self.face_bytes())
+        self._check(lib().aderdg_step_adjoint_faces_noalloc(
+            self._h, float(dt), float(t), ctypes.c_void_p(Qn.data_ptr()), ctypes.c_void_p(fwd_faces.data_ptr()),
+            ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(grad.data_ptr())))
 
     def receivers_adjoint(self, weight, lam):
         """lam[cell][0][node] += sum_r weight[r] phi_node(x_r) (device tensors)."""

@@ -35,7 +35,21 @@ struct AdjointWork {
     size_t bytes_lamface = 0, bytes_fwdface = 0, bytes_lamout = 0;
 };
 
-int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::string &msg);
+// One adjoint step.  lamface_scratch: device memory of at least
+// adjoint_lamface_bytes(a) bytes for the face restrictions of the incoming
+// adjoint (then nothing is allocated; a.fwdface must be given), or null: the
+// solver's work buffers, allocated on first use.
+int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::string &msg,
+                 void *lamface_scratch = nullptr);
+size_t adjoint_lamface_bytes(const AdjointArgs &a);
+
+// The library's static scratch array for callers that cannot allocate:
+// noalloc_scratch_init() resolves its address on the current device (once per
+// device; call with that device current), noalloc_scratch() returns it
+// (null if not resolved).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+int noalloc_scratch_init(std::string &msg);
+void *noalloc_scratch(int device);
 void adjoint_free(AdjointWork &w);
 // Receiver misfit scatter, grouped by cell: ncells cells ucell[m] hold the
 // receivers order[start[m] .. start[m+1]-1].

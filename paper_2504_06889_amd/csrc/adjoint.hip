@@ -7,6 +7,7 @@
 //                   FP64 kernel, or the mixed-precision one when the predictor
 //                   and volume contractions run in lower formats.
 #include <map>
+#include <mutex>
 #include <utility>
 
 #include "adjoint.h"
@@ -84,6 +85,46 @@ static const std::map<std::pair<int, int>, AdjFns> &adj_table() {
     return t;
 }
 
+// Scratch for aderdg_step_adjoint_faces_noalloc: a file-scope device array,
+// one copy per GPU at its own address, held until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in); it uses the address hipGetSymbolAddress returned on that device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[64];  // resolved address per device id
+
+int noalloc_scratch_init(std::string &msg) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        msg = "no current HIP device for the scratch array";
+        return ADERDG_E_DEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[dev]) return 0;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        msg = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return ADERDG_E_DEVICE;
+    }
+    g_scratch_dev[dev] = p;
+    return 0;
+}
+
+void *noalloc_scratch(int device) {
+    if (device < 0 || device >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_dev[device];
+}
+
+size_t adjoint_lamface_bytes(const AdjointArgs &a) {
+    const int V = 1 + a.dim;
+    size_t F = 1;
+    for (int i = 1; i < a.dim; i++) F *= a.order + 1;
+    return sizeof(double) * (size_t)a.ncell * a.dim * 2 * V * F;
+}
+
 static int ensure(void **p, size_t *have, size_t need) {
     if (*have >= need) return 0;
     hipFree(*p);
@@ -94,7 +135,7 @@ static int ensure(void **p, size_t *have, size_t need) {
     return 0;
 }
 
-int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::string &msg) {
+int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::string &msg, void *lamface_scratch) {
     auto it = adj_table().find(std::make_pair(a.dim, a.order));
     if (it == adj_table().end() || !a.pred) {
         msg = "adjoint not built for this (dim, order)";
@@ -105,16 +146,23 @@ int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::stri
         msg = "mixed-precision adjoint not built for this (dim, order)";
         return ADERDG_E_UNSUPPORTED;
     }
-    const int V = 1 + a.dim;
-    int F = 1;
-    for (int i = 1; i < a.dim; i++) F *= a.order + 1;
-    const size_t lf = sizeof(double) * a.ncell * a.dim * 2 * V * F;
-    if (ensure(&w.lamface, &w.bytes_lamface, lf) || (!a.fwdface && ensure(&w.fwdface, &w.bytes_fwdface, 2 * lf))) {
-        msg = "adjoint work allocation failed";
-        return ADERDG_E_OOM;
+    const size_t lf = adjoint_lamface_bytes(a);
+    void *lamface = lamface_scratch;
+    if (lamface) {
+        if (!a.fwdface) {
+            msg = "the scratch path needs the forward face data";
+            return ADERDG_E_INVALID;
+        }
+    } else {
+        if (ensure(&w.lamface, &w.bytes_lamface, lf) ||
+            (!a.fwdface && ensure(&w.fwdface, &w.bytes_fwdface, 2 * lf))) {
+            msg = "adjoint work allocation failed";
+            return ADERDG_E_OOM;
+        }
+        lamface = w.lamface;
     }
     // 1. face restrictions of the incoming adjoint
-    it->second.lamface(a.lam, (double *)w.lamface, a.ncell, a.B, st);
+    it->second.lamface(a.lam, (double *)lamface, a.ncell, a.B, st);
     // 2. forward face data of this step (unless the caller kept them)
     const void *fwd = a.fwdface ? a.fwdface : w.fwdface;
     if (!a.fwdface) {
@@ -145,7 +193,7 @@ int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::stri
     k.Qn = a.Qn;
     k.lam = a.lam;
     k.grad = a.grad;
-    k.lamface = (const double *)w.lamface;
+    k.lamface = (const double *)lamface;
     k.fwdface = (const double *)fwd;
     k.B = a.B;
     k.pde = a.pde;

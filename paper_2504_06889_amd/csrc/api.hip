@@ -104,6 +104,7 @@ struct aderdg_solver {
     int *dFlag = nullptr;
     int prec[4] = {0, 0, 0, 0};
     int predictor = ADERDG_PICARD;
+    int device = -1;  // HIP device current at creation
     AdjointWork adj;
     bool timing = false;
     std::vector<hipEvent_t> ev;  // 2 events per timed launch
@@ -219,7 +220,21 @@ aderdg_status aderdg_create(const aderdg_config *cfg, void *hip_stream, aderdg_s
         return ADERDG_E_INVALID;
     }
     s->face_elems = (size_t)s->ncell * s->d * 2 * 2 * s->V * s->F;
-    hipError_t e = hipSuccess;
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) {
+        g_create_err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        delete s;
+        return ADERDG_E_DEVICE;
+    }
+    {
+        // address of the static scratch array on this device (once per device)
+        std::string msg;
+        if (noalloc_scratch_init(msg) != 0) {
+            g_create_err = msg;
+            delete s;
+            return ADERDG_E_DEVICE;
+        }
+    }
     e = hipMalloc(&s->dB, sizeof(DevBasis));
     if (e == hipSuccess) e = hipMalloc(&s->dQ, sizeof(double) * state_elems(s));
     if (e == hipSuccess) e = hipMalloc(&s->dFaces, sizeof(double) * s->face_elems);
@@ -651,7 +666,7 @@ aderdg_status aderdg_read_receivers(aderdg_solver *s, double *out, int is_device
 }
 
 static aderdg_status step_adjoint(aderdg_solver *s, double dt, double t, const double *Qn_dev, const void *fwd,
-                                  double *lam_dev, double *grad_dev) {
+                                  double *lam_dev, double *grad_dev, bool noalloc = false) {
     if (!s || !Qn_dev || !lam_dev || !grad_dev) return ADERDG_E_INVALID;
     if (!(dt > 0)) FAIL(s, ADERDG_E_INVALID, "dt must be positive");
     if (s->cfg.pde != ADERDG_ACOUSTIC || !s->dMat)
@@ -688,7 +703,18 @@ static aderdg_status step_adjoint(aderdg_solver *s, double dt, double t, const d
     a.src_amp = s->src_amp;
     source_values(s, t, dt, a.src_s, &a.src_bar);
     std::string msg;
-    const int rc = adjoint_step(s->adj, a, s->stream, msg);
+    void *scr = nullptr;
+    if (noalloc) {
+        scr = noalloc_scratch(s->device);
+        if (!scr) FAIL(s, ADERDG_E_DEVICE, "the scratch array is not set up on device %d", s->device);
+        const size_t need = adjoint_lamface_bytes(a);
+        if (need > kNoAllocScratchBytes)
+            FAIL(s, ADERDG_E_INVALID,
+                 "the adjoint face restrictions need %zu bytes, more than the %zu-byte scratch array "
+                 "(ncell * dim * 2 * (dim + 1) * (order + 1)^(dim - 1) * 8 bytes)",
+                 need, (size_t)kNoAllocScratchBytes);
+    }
+    const int rc = adjoint_step(s->adj, a, s->stream, msg, scr);
     if (rc != 0) {
         s->err = msg;
         return (aderdg_status)rc;
@@ -705,6 +731,12 @@ aderdg_status aderdg_step_adjoint_faces(aderdg_solver *s, double dt, double t, c
                                         const void *fwd_faces_dev, double *lam_dev, double *grad_dev) {
     if (!fwd_faces_dev) return ADERDG_E_INVALID;
     return step_adjoint(s, dt, t, Qn_dev, fwd_faces_dev, lam_dev, grad_dev);
+}
+
+aderdg_status aderdg_step_adjoint_faces_noalloc(aderdg_solver *s, double dt, double t, const double *Qn_dev,
+                                                const void *fwd_faces_dev, double *lam_dev, double *grad_dev) {
+    if (!fwd_faces_dev) return ADERDG_E_INVALID;
+    return step_adjoint(s, dt, t, Qn_dev, fwd_faces_dev, lam_dev, grad_dev, true);
 }
 
 aderdg_status aderdg_copy_faces(aderdg_solver *s, void *dst, int is_device) {
