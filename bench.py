@@ -70,16 +70,17 @@ def corrector_flops(d, N, V):
     return 2 * d * F * (6 * V + 20) + 4 * d * V * S
 
 
-def fused_bytes(d, N, V, face_bytes, q_only):
+def fused_bytes(d, N, V, face_bytes, q_only, state_bytes=8):
     """HBM bytes per cell of one fused launch (corrector of the previous step +
-    predictor): Q* read and written (FP64), the previous face data of the cell and of
-    its neighbours read, the new face data written.  For a linear PDE with FP64 faces
-    only the projected q is stored."""
+    predictor): Q* read and written (state_bytes per value: 8 for FP64 storage, 4 or 2
+    for a narrower storage format), the previous face data of the cell and of its
+    neighbours read, the new face data written.  For a linear PDE with FP64 faces only
+    the projected q is stored."""
     n = N + 1
     S = n ** d
     F = S // n
     faces = 2 * d * V * F * face_bytes * (1 if q_only else 2)
-    return 2 * S * V * 8 + 2 * faces + faces
+    return 2 * S * V * state_bytes + 2 * faces + faces
 
 
 # Sources that determine the machine code of k_predictor for this workload.
@@ -133,7 +134,7 @@ def measured_mfma_busy(workload="elastic3d_n5_64"):
     return profile_values("profiles/k_predictor_%s_sq_counters.md" % workload, "mfma-busy-cycles-per-launch")
 
 
-def roofline(pde, d, N, V, I, ncell, t, prec, q_only, traffic=None, mfma_busy=None):
+def roofline(pde, d, N, V, I, ncell, t, prec, q_only, traffic=None, mfma_busy=None, state_bytes=8):
     """Roofline entry of one fused launch (corrector of the previous step + predictor)
     taking t seconds: the achieved fraction of each published peak the launch's
     algorithmic work touches -- HBM bytes / 8 TB/s, the matrix-core contraction flops
@@ -145,7 +146,7 @@ def roofline(pde, d, N, V, I, ncell, t, prec, q_only, traffic=None, mfma_busy=No
     mfma_busy: SQ_VALU_MFMA_BUSY_CYCLES per launch summed over SIMDs (or None)."""
     mf, v64, fl = predictor_flops(pde, d, N, V, I)
     v64 += corrector_flops(d, N, V)
-    hbm = fused_bytes(d, N, V, 8, q_only) * ncell
+    hbm = fused_bytes(d, N, V, 8, q_only, state_bytes) * ncell
     total = (mf + v64 + fl) * ncell
     fr = {"hbm": hbm / t / PEAK["hbm"]}
     times = {"hbm": hbm / PEAK["hbm"]}
@@ -431,12 +432,12 @@ def workload_runs(name):
         if ref_o is not None:
             ids = torch.from_numpy(ref_o["ids"]).cuda()
             r.update(vs_oracle(ref_o, st.index_select(0, ids).cpu().numpy(), Wn))
-        # roofline of the fused kernel where the predictor's format sets its kind
-        if prec[0] == prec[1] or prec[0] == "fp64":
-            key = "fp64" if prec == ("fp64",) * 3 else label
-            r["roofline"] = roofline(sc.pde, sc.dim, sc.order, g.V, g.iters, g.ncell, fused * 1e-3,
-                                     prec[0] if prec[0] != "fp64" else "fp64", sc.pde in ("acoustic", "elastic")
-                                     and prec[2] == "fp64", traffic.get(key), busy.get(key))
+        # roofline of the fused kernel, its contraction flops counted in the
+        # predictor's format (the volume contraction is a few per cent of them)
+        key = "fp64" if prec == ("fp64",) * 3 else label
+        r["roofline"] = roofline(sc.pde, sc.dim, sc.order, g.V, g.iters, g.ncell, fused * 1e-3, prec[0],
+                                 sc.pde in ("acoustic", "elastic") and prec[2] == "fp64", traffic.get(key),
+                                 busy.get(key))
         runs[label] = r
         print("%s %s: %s" % (name, label, ", ".join("%s %.4g" % (k, v) for k, v in r.items()
                                                    if isinstance(v, float))), file=sys.stderr, flush=True)
@@ -486,14 +487,14 @@ def paper_table_runs():
         elif kernel == "all":
             pr = vo = fl = p
         return (pr, vo, fl, base)
-    runs = [("storage32:reference", ("fp32",) * 4)]
+    runs = [("storage_fp32:reference", ("fp32",) * 4)]
     for p in ("bf16", "fp16"):
         for k in ("Picard", "predictor", "corrector", "all"):
-            runs.append(("storage32:%s=%s" % (k, p), one(k, p, "fp32")))
+            runs.append(("storage_fp32:%s=%s" % (k, p), one(k, p, "fp32")))
     for base in ("bf16", "fp16", "fp32"):
-        runs.append(("base%s:reference" % base[2:], (base,) * 4))
+        runs.append(("base_%s:reference" % base, (base,) * 4))
         for k in ("Picard", "predictor", "corrector", "all"):
-            runs.append(("base%s:%s=fp64" % (base[2:], k), one(k, "fp64", base)))
+            runs.append(("base_%s:%s=fp64" % (base, k), one(k, "fp64", base)))
     return runs
 
 
@@ -559,7 +560,7 @@ def paper_suite():
         out[name] = paper_suite_runs(sc, PAPER_RUNS[1:] + table)
     for name in ("euler2d_n5_27_bell", "euler2d_n5_27_vortex"):
         sc = inputs.PAPER_SUITE[name].with_cells((81, 81))
-        fine = [(k, p) for k, p in table if k.startswith("base32:")]
+        fine = [(k, p) for k, p in table if k.startswith("base_fp32:")]
         out[name.replace("_27_", "_81_")] = paper_suite_runs(sc, fine)
     return out
 
@@ -571,6 +572,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="elastic3d_n5_64")
     ap.add_argument("--variants", default="fp64,fp32,bf16,fp16")
+    ap.add_argument("--storage", default="fp64", choices=("fp64", "fp32", "bf16", "fp16"),
+                    help="storage format of the state in the timed runs of the headline workload")
     ap.add_argument("--ck-variants", default="fp64,fp16",
                     help="precisions run with the Cauchy-Kowalevskaya predictor (linear PDEs), reported beside")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -653,6 +656,7 @@ def main():
         prec = ("fp64", "fp64", "fp64") if p == "fp64" else (p, p, "fp64")
         g.set_predictor(kind)
         g.set_precisions(*prec)
+        g.set_precision("storage", args.storage)
         g.set_state(Q0)
         g.time = 0.0
         g.step(dt, args.warmup)
@@ -669,7 +673,8 @@ def main():
         g.get_state(out)
         p = label
         states[p] = out
-        runs[p] = {"predictor": kind, "precisions": {"predictor": prec[0], "volume": prec[1], "flux": prec[2]},
+        runs[p] = {"predictor": kind, "precisions": {"predictor": prec[0], "volume": prec[1], "flux": prec[2],
+                                                     "storage": args.storage},
                    "ms_per_step": 1e3 * el / args.steps, "dof_per_s": dof * args.steps / el,
                    "kernel_ms_per_step": (tm["predictor_ms"] + tm["corrector_ms"] + tm["fused_ms"]) / max(tm["steps"], 1),
                    "fused_kernel_ms": tm["fused_ms"] / max(tm["fused_launches"], 1),
@@ -699,9 +704,12 @@ def main():
     for p in runs:
         if runs[p]["predictor"] != "picard":
             continue
+        st = args.storage
         runs[p]["roofline"] = roofline(sc.pde, sc.dim, sc.order, g.V, g.iters, g.ncell,
                                        runs[p]["fused_kernel_ms"] * 1e-3, p, sc.pde in ("acoustic", "elastic"),
-                                       traffic.get(p), busy.get(p))
+                                       traffic.get(p if st == "fp64" else "%s+storage_%s" % (p, st)),
+                                       busy.get(p) if st == "fp64" else None,
+                                       {"fp64": 8, "fp32": 4}.get(st, 2))
 
     # the workload's own number of steps from the initial state, each variant
     # against the full-length FP64 oracle reference at its sampled cells

@@ -141,6 +141,7 @@ struct Acoustic {  // eq. acoustic: p_t + K div v = 0, rho v_t + grad p = 0
     static constexpr int V = 1 + DIM;
     static constexpr bool kNCP = false;
     static constexpr bool kLinear = true;
+    static constexpr bool kPointSource = true;  // a point source may act on p
     struct Coef { double K, irho, c; };
     __device__ static Coef cell(const PdeArgs &a, long cell) {
         Coef c;
@@ -170,6 +171,7 @@ struct Elastic {  // eq. equations_of_motion, q_t + A_j q_{x_j} = 0
     static constexpr int NS = DIM * (DIM + 1) / 2;
     static constexpr bool kNCP = false;
     static constexpr bool kLinear = true;
+    static constexpr bool kPointSource = false;
     struct Coef { double lam, mu, irho, cp; };
     __device__ static Coef cell(const PdeArgs &a, long) {
         Coef c;
@@ -216,6 +218,7 @@ struct Euler {  // conserved (rho, rho v, E), ideal gas
     static constexpr int V = 2 + DIM;
     static constexpr bool kNCP = false;
     static constexpr bool kLinear = false;
+    static constexpr bool kPointSource = false;
     struct Coef { double g; };
     __device__ static Coef cell(const PdeArgs &a, long) { return Coef{a.prm[0]}; }
     template <class T>
@@ -247,6 +250,7 @@ struct Swe {  // (h, hu, hv, b); pressure term as non-conservative g h grad(h+b)
     static constexpr int V = 4;
     static constexpr bool kNCP = true;
     static constexpr bool kLinear = false;
+    static constexpr bool kPointSource = false;
     struct Coef { double g; };
     __device__ static Coef cell(const PdeArgs &a, long) { return Coef{a.prm[0]}; }
     template <class T>

@@ -647,7 +647,9 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     for (int v = 0; v < V; v++) vol[v] = 0.0;
     bool vol_done = false;  // formed on the matrix cores with the predictor's buffers
 
-    const bool src_here = active && cell == a.src_cell;
+    // (point sources act on acoustics only: for the other systems the source
+    // terms are compiled out and hold no registers)
+    const bool src_here = Pde::kPointSource && active && cell == a.src_cell;
     const double src_phi = src_here ? a.src_phi[s] : 0.0;
     const int iters = a.iters;
 

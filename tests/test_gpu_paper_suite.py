@@ -52,13 +52,13 @@ def test_lower_format_contractions(oracle_mod, name, p):
 
 # the settings of the paper's FP32-storage table and its table of one kernel in
 # FP64 on a lower base, as (predictor, volume, flux, storage)
-TABLE_CASES = [("storage32:Picard=bf16", ("bf16", "fp32", "fp32", "fp32")),
-               ("storage32:predictor=fp16", ("fp16", "fp16", "fp32", "fp32")),
-               ("storage32:corrector=bf16", ("fp32", "fp32", "bf16", "fp32")),
-               ("base16:reference", ("fp16",) * 4),
-               ("base16:predictor=fp64", ("fp64", "fp64", "fp16", "fp16")),
-               ("base32:corrector=fp64", ("fp32", "fp32", "fp64", "fp32")),
-               ("basebf16:all=fp64", ("fp64", "fp64", "fp64", "bf16"))]
+TABLE_CASES = [("storage_fp32:Picard=bf16", ("bf16", "fp32", "fp32", "fp32")),
+               ("storage_fp32:predictor=fp16", ("fp16", "fp16", "fp32", "fp32")),
+               ("storage_fp32:corrector=bf16", ("fp32", "fp32", "bf16", "fp32")),
+               ("base_fp16:reference", ("fp16",) * 4),
+               ("base_fp16:predictor=fp64", ("fp64", "fp64", "fp16", "fp16")),
+               ("base_fp32:corrector=fp64", ("fp32", "fp32", "fp64", "fp32")),
+               ("base_bf16:all=fp64", ("fp64", "fp64", "fp64", "bf16"))]
 
 
 @pytest.mark.parametrize("name", ["acoustic2d_n5_27_planar", "euler2d_n5_27_bell"])
