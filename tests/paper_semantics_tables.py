@@ -1,7 +1,9 @@
 """The paper's 2-D scenarios under the oracle's emulation of the paper's own
 precision semantics (each kernel computes, accumulates and stores in its type;
 Sec. 4.1, the runs of Sec. 7), on a reduced grid, for comparison of trends with
-the paper's tables and with the GPU path's runs of the same settings.
+the paper's tables and with the GPU path's runs of the same settings; with
+--semantics build the same settings run under the emulation of the library's own
+rounding points instead, on the same grid.
 
 Not collected by pytest (a script of the test infrastructure): it runs the CPU
 oracle only and prints one JSON line per scenario.  Settings are (predictor,
@@ -10,6 +12,7 @@ kernel (Picard loop, time averages, face projection, volume integral), its Picar
 loop takes the Picard type, "corrector" the Riemann solve and surface integral.
 
     python tests/paper_semantics_tables.py --cells 9 --threads 4
+    python tests/paper_semantics_tables.py --cells 9 --threads 4 --semantics build
 """
 import argparse
 import json
@@ -44,13 +47,24 @@ def settings():
     return out
 
 
-def run(name, cells):
+def make(sc, pr, pq, co, st, semantics):
+    """The oracle in one setting.  Under the paper's semantics the Picard loop has a
+    type of its own; under the library's (rounding points of the GPU kernels) the
+    Picard loop is the PREDICTOR kernel and the rest of the paper's predictor
+    kernel (time averages, projection, volume integral) the VOLUME kernel."""
+    if semantics == "paper":
+        return oracle.Oracle(sc.dim, sc.order, sc.cells, sc.lo, sc.hi, sc.pde, sc.params, prec=(pr, "fp64", co),
+                             storage=st, semantics="paper", prec_picard=pq)
+    return oracle.Oracle(sc.dim, sc.order, sc.cells, sc.lo, sc.hi, sc.pde, sc.params, prec=(pq, pr, co),
+                         storage=st)
+
+
+def run(name, cells, semantics="paper"):
     sc = inputs.PAPER_SUITE[name].with_cells((cells, cells))
     res = {}
     ref = None
     for label, pr, pq, co, st in settings():
-        o = oracle.Oracle(sc.dim, sc.order, sc.cells, sc.lo, sc.hi, sc.pde, sc.params, prec=(pr, "fp64", co),
-                          storage=st, semantics="paper", prec_picard=pq)
+        o = make(sc, pr, pq, co, st, semantics)
         X = o.node_coords()
         Q0 = sc.initial_state(X)
         o.set_state(Q0)
@@ -81,16 +95,17 @@ def run(name, cells):
         print(name, label, {k: ("%.3g" % v if isinstance(v, float) else v) for k, v in r.items()},
               file=sys.stderr, flush=True)
     return {"cells": [cells, cells], "order": sc.order, "t_end": sc.extra["t_end"], "steps": nsteps, "dt": dt,
-            "runs": res}
+            "semantics": semantics, "runs": res}
 
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--cells", type=int, default=9)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--semantics", choices=["paper", "build"], default="paper")
     ap.add_argument("names", nargs="*")
     args = ap.parse_args()
     if args.threads:
         oracle.set_num_threads(args.threads)
     for nm in args.names or list(inputs.PAPER_SUITE):
-        print(json.dumps({nm: run(nm, args.cells)}), flush=True)
+        print(json.dumps({nm: run(nm, args.cells, args.semantics)}), flush=True)
