@@ -175,11 +175,12 @@ aderdg_status aderdg_step_adjoint(aderdg_solver *s, double dt, double t, const d
                                   double *lam_dev, double *grad_dev);
 
 /* The face data of the last step's predictor (the time-averaged q and F_j
- * projected to both sides of every face, Alg. 1 "expansion"), layout
- * [cell][dir][side][q|f][var][face node] in the FLUX format, info[7] bytes per
- * cell, copied to dst (device if is_device, else host; a host copy
- * synchronises).  For a linear PDE with FP64 faces the f half is not written
- * (the corrector evaluates the flux from the projected q).  Valid after
+ * projected to both sides of every face, Alg. 1 "expansion"), copied to dst
+ * (device if is_device, else host; a host copy synchronises), info[7] bytes per
+ * cell in the FLUX format: layout [cell][dir][side][q|f][var][face node], or,
+ * for a linear PDE with FP64 faces, whose f halves the predictor does not write
+ * (the corrector evaluates the flux from the projected q),
+ * [cell][dir][side][var][face node] with the q halves only.  Valid after
  * aderdg_step; dst is owned by the caller.                                  */
 aderdg_status aderdg_copy_faces(aderdg_solver *s, void *dst, int is_device);
 
@@ -217,7 +218,7 @@ aderdg_status aderdg_receivers_adjoint(aderdg_solver *s, const double *weight_de
 aderdg_status aderdg_nodes(int n, double *xi, double *w);
 
 /* info[0..7] = n, dim, V, S (= n^dim), F (= n^(dim-1)), Picard iterations,
- * cells (total), face buffer bytes per cell.                                */
+ * cells (total), bytes per cell that aderdg_copy_faces writes.              */
 aderdg_status aderdg_info(const aderdg_solver *s, long long *info);
 
 /* Device pointer of the state (for zero-copy use by the caller; stream-ordered).

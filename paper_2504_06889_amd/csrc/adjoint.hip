@@ -195,6 +195,9 @@ int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::stri
     k.grad = a.grad;
     k.lamface = (const double *)lamface;
     k.fwdface = (const double *)fwd;
+    // the predictor's own buffer holds both halves; a caller's copy holds the q
+    // halves only (aderdg_copy_faces of a linear PDE with FP64 faces)
+    k.fwd_halves = a.fwdface ? 1 : 2;
     k.B = a.B;
     k.pde = a.pde;
     k.ncell = a.ncell;

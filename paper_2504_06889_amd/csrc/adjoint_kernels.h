@@ -42,7 +42,8 @@ struct AdjKArgs {
     double *lam;           // in: adjoint after the step; out: adjoint at the start
     double *grad;          // += d<lam, step>/dc per cell
     const double *lamface; // [cell][dir][side][V][F]: L_side^T contracted lam
-    const double *fwdface; // forward face data of the step [cell][dir][side][q|f][V][F]
+    const double *fwdface; // forward face data of the step [cell][dir][side][half][V][F]
+    int fwd_halves;        // halves per face side in fwdface: 2 ([q|f]) or 1 (q only)
     const DevBasis *B;
     PdeArgs pde;
     long ncell;
@@ -427,8 +428,8 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
                 const double lL = a.lamface[(((cl * DIM + j) * 2 + 1) * V + v) * (long)F + f];
                 const double G = a.sigma * (lR - lL);
                 gmax = fmax(gmax, fabs(G));
-                const double qm = a.fwdface[((((cl * DIM + j) * 2 + 1) * 2 + 0) * V + v) * (long)F + f];
-                const double qp = a.fwdface[((((cr * DIM + j) * 2 + 0) * 2 + 0) * V + v) * (long)F + f];
+                const double qm = a.fwdface[(((cl * DIM + j) * 2 + 1) * a.fwd_halves * V + v) * (long)F + f];
+                const double qp = a.fwdface[(((cr * DIM + j) * 2 + 0) * a.fwd_halves * V + v) * (long)F + f];
                 sbar += -0.5 * G * (qp - qm);
                 const int o = (((cbi * DIM + j) * 2 + side) * V + v) * F + f;
                 gq[o] = (side ? 0.5 : -0.5) * sp * G;

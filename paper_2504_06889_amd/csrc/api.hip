@@ -48,6 +48,15 @@ __global__ __launch_bounds__(256) void k_convert_state(const void *src, int sp_s
         store_state(dst, i, load_state(src, i, sp_src), sp_dst);
 }
 
+// dst[r][k] = src[r][k] for the first of the two halves of every row:
+// rows of 2 * hw doubles in, hw doubles out.
+__global__ __launch_bounds__(256) void k_copy_first_halves(double *dst, const double *src, long hw, long n) {
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+        const long r = i / hw;
+        dst[i] = src[i + r * hw];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_nonfinite(const void *x, int sp, long n, int *flag) {
     int bad = 0;
     for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256)
@@ -739,13 +748,28 @@ aderdg_status aderdg_step_adjoint_faces_noalloc(aderdg_solver *s, double dt, dou
     return step_adjoint(s, dt, t, Qn_dev, fwd_faces_dev, lam_dev, grad_dev, true);
 }
 
+// The predictor leaves the f halves of the face buffer unwritten when the
+// corrector evaluates the flux from the projected q: a linear PDE with FP64
+// faces.  Copies of the face data then hold the q halves only.
+static bool faces_q_only(const aderdg_solver *s) {
+    return (s->cfg.pde == ADERDG_ACOUSTIC || s->cfg.pde == ADERDG_ELASTIC) && s->prec[ADERDG_K_FLUX] == ADERDG_FP64;
+}
+
 aderdg_status aderdg_copy_faces(aderdg_solver *s, void *dst, int is_device) {
     if (!s || !dst) return ADERDG_E_INVALID;
-    long long info[8];
-    aderdg_info(s, info);
-    const size_t bytes = (size_t)info[7] * (size_t)s->ncell;
-    HIPC(s, hipMemcpyAsync(dst, s->dFaces, bytes, is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                           s->stream));
+    const hipMemcpyKind kind = is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const int fp = s->prec[ADERDG_K_FLUX];
+    const size_t half = (size_t)s->V * s->F * (fp == 0 ? 8 : (fp == 1 ? 4 : 2));  // one [var][face node] block
+    const size_t rows = (size_t)s->ncell * s->d * 2;                                // (cell, dir, side)
+    if (faces_q_only(s) && is_device) {  // FP64 halves: whole doubles
+        const long hw = (long)(half / sizeof(double)), n = hw * (long)rows;
+        hipLaunchKernelGGL(k_copy_first_halves, dim3(grid256(n)), dim3(256), 0, s->stream, (double *)dst,
+                           (const double *)s->dFaces, hw, n);
+        HIPC(s, hipGetLastError());
+    } else if (faces_q_only(s)) {
+        HIPC(s, hipMemcpy2DAsync(dst, half, s->dFaces, 2 * half, half, rows, kind, s->stream));
+    } else
+        HIPC(s, hipMemcpyAsync(dst, s->dFaces, 2 * half * rows, kind, s->stream));
     if (!is_device) HIPC(s, hipStreamSynchronize(s->stream));
     return ADERDG_OK;
 }
@@ -775,7 +799,7 @@ aderdg_status aderdg_info(const aderdg_solver *s, long long *info) {
     info[5] = s->iters;
     info[6] = s->ncell;
     const int fp = s->prec[ADERDG_K_FLUX];
-    info[7] = (long long)(2 * s->d * 2 * s->V * s->F) * (fp == 0 ? 8 : (fp == 1 ? 4 : 2));
+    info[7] = (long long)(2 * s->d * (faces_q_only(s) ? 1 : 2) * s->V * s->F) * (fp == 0 ? 8 : (fp == 1 ? 4 : 2));
     return ADERDG_OK;
 }
 
