@@ -717,7 +717,13 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 if (bb == b) z[bb][v] = (RowT)r;
         }
     };
-    // end of an iteration > 0: rows hold h R_b; replace them by the new iterate
+    // end of an iteration > 0: rows hold h R_b; replace them by the new iterate.
+    // After the last iteration of a linear system without non-conservative
+    // term only the time average of the iterate is used (the flux average is
+    // F_j(qbar)), and as the weights sum to one it is
+    // sum_a w_a q_a = Qn - sigma sum_b wA[b] h R_b: n FMAs per variable
+    // instead of n^2 + n (the same value up to FP64 rounding).
+    constexpr bool QDIRECT = Pde::kLinear && !Pde::kNCP;
     auto update = [&](bool last) __attribute__((always_inline)) {
 #pragma unroll
         for (int v = 0; v < V; v++) {
@@ -727,14 +733,19 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 r[b] = (double)z[b][v];
                 if (FR && v == 0 && src_here) r[b] -= src_term(b);
             }
+            if (QDIRECT && last) {
+                double acc = 0.0;
+#pragma unroll
+                for (int b = 0; b < n; b++) acc = fma(B->wA[b], r[b], acc);
+                qbar[v] = fma(-a.sigma, acc, Qn[v]);
+                continue;
+            }
 #pragma unroll
             for (int t = 0; t < n; t++) {
                 double acc = 0.0;
 #pragma unroll
                 for (int b = 0; b < n; b++) acc = fma(B->Atau[t][b], r[b], acc);
-                const double qt = fma(-a.sigma, acc, Qn[v]);
-                if (FR && last) qbar[v] = fma(B->w[t], qt, qbar[v]);
-                z[t][v] = (RowT)qt;
+                z[t][v] = (RowT)fma(-a.sigma, acc, Qn[v]);
             }
         }
     };
@@ -813,15 +824,16 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         if (ck) {
             if constexpr (CKOK) ck_run(slice);
         } else {
+            // the last update is peeled off the loop (it may form qbar directly)
+            slice(z[0], [&](int v, double r) __attribute__((always_inline)) { fold(0, 0, v, r, iters == 1); });
 #pragma unroll 1
-            for (int it = 0; it < iters; it++) {
+            for (int it = 1; it < iters; it++) {
 #pragma unroll
-                for (int b = 0; b < n; b++) {
-                    if (it == 0 && b > 0) continue;
-                    slice(z[b], [&](int v, double r) __attribute__((always_inline)) { fold(it, b, v, r, iters == 1); });
-                }
-                if (it > 0 && active) update(it == iters - 1);
+                for (int b = 0; b < n; b++)
+                    slice(z[b], [&](int v, double r) __attribute__((always_inline)) { fold(it, b, v, r, false); });
+                if (it < iters - 1 && active) update(false);
             }
+            if (iters > 1 && active) update(true);
         }
     } else {
         using T = typename Store<PP>::T;
@@ -990,7 +1002,8 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     for (int v = 0; v < V; v++) {
         nbar[v] = 0.0;
         if constexpr (!FR) {
-            if (!ck) {
+            // (formed by the last update when it was direct)
+            if (!ck && !(QDIRECT && iters > 1)) {
 #pragma unroll
                 for (int t = 0; t < n; t++) qbar[v] = fma(B->w[t], z[t][v], qbar[v]);
             }
