@@ -13,6 +13,7 @@ struct AdjointArgs {
     long ncell;
     int cells[3];
     const DevBasis *B;
+    const ScaledTime *st;  // the time operator scaled by -sigma for dt (forward predictor)
     PdeArgs pde;
     double dt, t, inv_h, sigma;
     int iters;

@@ -170,6 +170,7 @@ int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::stri
         f.Q = const_cast<double *>(a.Qn);
         f.faces = w.fwdface;
         f.B = a.B;
+        f.st = a.st;
         f.pde = a.pde;
         f.ncell = a.ncell;
         for (int i = 0; i < 3; i++) f.cells[i] = a.cells[i];

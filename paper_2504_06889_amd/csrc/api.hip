@@ -57,6 +57,17 @@ __global__ __launch_bounds__(256) void k_copy_first_halves(double *dst, const do
     }
 }
 
+// -sigma times the time operator, its row sums and weighted column sums
+// (one 64-thread block; kMaxN^2 = 64).
+__global__ __launch_bounds__(64) void k_scale_time(const DevBasis *B, double sigma, ScaledTime *o) {
+    const int i = threadIdx.x, r = i / kMaxN, c = i % kMaxN;
+    o->At[r][c] = -sigma * B->Atau[r][c];
+    if (i < kMaxN) {
+        o->Arow[i] = -sigma * B->Arow[i];
+        o->wA[i] = -sigma * B->wA[i];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_nonfinite(const void *x, int sp, long n, int *flag) {
     int bad = 0;
     for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256)
@@ -94,6 +105,7 @@ struct aderdg_solver {
     const KernelSet *ks;
     DevBasis hB;
     DevBasis *dB = nullptr;
+    ScaledTime *dST = nullptr;  // time operator scaled for the dt of the last step call
     void *dQ = nullptr;         // state in the storage precision prec[ADERDG_K_STORAGE]
     void *dFaces = nullptr;     // face data of the last predictor
     void *dFaces2 = nullptr;    // second buffer: a fused step reads one and writes the other
@@ -142,6 +154,7 @@ static void free_all(aderdg_solver *s) {
     for (auto e : s->ev) hipEventDestroy(e);
     s->ev.clear();
     hipFree(s->dB);
+    hipFree(s->dST);
     hipFree(s->dQ);
     hipFree(s->dFaces);
     hipFree(s->dFaces2);
@@ -245,6 +258,7 @@ aderdg_status aderdg_create(const aderdg_config *cfg, void *hip_stream, aderdg_s
         }
     }
     e = hipMalloc(&s->dB, sizeof(DevBasis));
+    if (e == hipSuccess) e = hipMalloc(&s->dST, sizeof(ScaledTime));
     if (e == hipSuccess) e = hipMalloc(&s->dQ, sizeof(double) * state_elems(s));
     if (e == hipSuccess) e = hipMalloc(&s->dFaces, sizeof(double) * s->face_elems);
     if (e == hipSuccess) e = hipMalloc(&s->dFaces2, sizeof(double) * s->face_elems);
@@ -438,12 +452,23 @@ static void source_values(const aderdg_solver *s, double t, double dt, double *s
     }
 }
 
+// Form the scaled time operator for step size dt on the solver's stream,
+// ahead of the launches that read it (every call, so that captured work
+// replays with its own dt).
+static aderdg_status scale_time(aderdg_solver *s, double dt) {
+    hipLaunchKernelGGL(k_scale_time, dim3(1), dim3(kMaxN * kMaxN), 0, s->stream, (const DevBasis *)s->dB, dt / s->h,
+                       s->dST);
+    HIPC(s, hipGetLastError());
+    return ADERDG_OK;
+}
+
 static StepArgs step_args(aderdg_solver *s, double dt, double t) {
     StepArgs a{};
     a.Q = s->dQ;
     a.faces = s->dFaces;
     a.faces_in = nullptr;
     a.B = s->dB;
+    a.st = s->dST;
     a.pde = pde_args(s);
     a.ncell = s->ncell;
     for (int i = 0; i < 3; i++) a.cells[i] = i < s->d ? s->cfg.cells[i] : 1;
@@ -500,6 +525,7 @@ aderdg_status aderdg_step(aderdg_solver *s, double dt, int nsteps) {
     const StepFn fused = s->ks->fused[s->prec[ADERDG_K_PREDICTOR]];
     const StepFn corr = s->ks->corr[s->prec[ADERDG_K_FLUX]];
     aderdg_status rc;
+    if ((rc = scale_time(s, dt)) != ADERDG_OK) return rc;
     StepArgs a = step_args(s, dt, s->t);
     if ((rc = launch(s, pred, a, 0)) != ADERDG_OK) return rc;
     for (int k = 1; k < nsteps; k++) {
@@ -695,6 +721,7 @@ static aderdg_status step_adjoint(aderdg_solver *s, double dt, double t, const d
     a.ncell = s->ncell;
     for (int i = 0; i < 3; i++) a.cells[i] = i < s->d ? s->cfg.cells[i] : 1;
     a.B = s->dB;
+    a.st = s->dST;
     a.pde = pde_args(s);
     a.dt = dt;
     a.t = t;
@@ -722,6 +749,10 @@ static aderdg_status step_adjoint(aderdg_solver *s, double dt, double t, const d
                  "the adjoint face restrictions need %zu bytes, more than the %zu-byte scratch array "
                  "(ncell * dim * 2 * (dim + 1) * (order + 1)^(dim - 1) * 8 bytes)",
                  need, (size_t)kNoAllocScratchBytes);
+    }
+    if (!a.fwdface) {  // the forward face data are recomputed with the predictor
+        const aderdg_status rs = scale_time(s, dt);
+        if (rs != ADERDG_OK) return rs;
     }
     const int rc = adjoint_step(s->adj, a, s->stream, msg, scr);
     if (rc != 0) {

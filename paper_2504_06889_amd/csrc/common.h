@@ -52,6 +52,16 @@ struct DevBasis {
 // change during a launch, so uniform reads become scalar loads.
 using CBasis = const __attribute__((address_space(4))) DevBasis;
 
+// The Picard time operator scaled by -sigma (sigma = dt/h) for one step size,
+// formed on the device from the basis before the step's launches: the update
+// q_a = Qn - sigma sum_b Atau[a][b] h R_b becomes one FMA chain from Qn.
+struct ScaledTime {
+    double At[kMaxN][kMaxN];  // -sigma Atau
+    double Arow[kMaxN];       // -sigma Arow
+    double wA[kMaxN];         // -sigma wA
+};
+using CScaled = const __attribute__((address_space(4))) ScaledTime;
+
 // ---------------------------------------------------------------------------
 // Precision conversions (round-to-nearest-even)
 // ---------------------------------------------------------------------------

@@ -32,6 +32,7 @@ struct StepArgs {
     void *faces;          // face buffer written by the predictor
     const void *faces_in; // fused step: the previous step's face buffer (corrector input)
     const DevBasis *B;
+    const ScaledTime *st; // the time operator scaled by -sigma for this dt
     PdeArgs pde;
     long ncell;
     int cells[3];
@@ -617,6 +618,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     __shared__ __attribute__((aligned(16))) char smem[L::bytes];
 
     CBasis *B = (CBasis *)a.B;
+    CScaled *ST = (CScaled *)a.st;
     const int tid = threadIdx.x;
     const int cb = tid / S, s = tid % S;
     const long blk = xcd_block(blockIdx.x, gridDim.x);
@@ -701,12 +703,11 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         if (it == 0) {
 #pragma unroll
             for (int t = 0; t < n; t++) {
-                double acc = B->Arow[t] * r;
+                double qt = fma(ST->Arow[t], r, Qn[v]);
                 if (v == 0 && src_here) {
 #pragma unroll
-                    for (int bb = 0; bb < n; bb++) acc = fma(B->Atau[t][bb], -src_term(bb), acc);
+                    for (int bb = 0; bb < n; bb++) qt = fma(ST->At[t][bb], -src_term(bb), qt);
                 }
-                const double qt = fma(-a.sigma, acc, Qn[v]);
                 if (FR && last) qbar[v] = fma(B->w[t], qt, qbar[v]);
                 z[t][v] = (RowT)qt;
             }
@@ -734,18 +735,18 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 if (FR && v == 0 && src_here) r[b] -= src_term(b);
             }
             if (QDIRECT && last) {
-                double acc = 0.0;
+                double acc = Qn[v];
 #pragma unroll
-                for (int b = 0; b < n; b++) acc = fma(B->wA[b], r[b], acc);
-                qbar[v] = fma(-a.sigma, acc, Qn[v]);
+                for (int b = 0; b < n; b++) acc = fma(ST->wA[b], r[b], acc);
+                qbar[v] = acc;
                 continue;
             }
 #pragma unroll
             for (int t = 0; t < n; t++) {
-                double acc = 0.0;
+                double acc = Qn[v];
 #pragma unroll
-                for (int b = 0; b < n; b++) acc = fma(B->Atau[t][b], r[b], acc);
-                z[t][v] = (RowT)fma(-a.sigma, acc, Qn[v]);
+                for (int b = 0; b < n; b++) acc = fma(ST->At[t][b], r[b], acc);
+                z[t][v] = (RowT)acc;
             }
         }
     };
