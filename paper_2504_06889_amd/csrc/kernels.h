@@ -188,6 +188,7 @@ struct MfmaPairs {
     __device__ void run(const T *X, float *Y, int wave, int lane) const {
         constexpr int TPW = (NTILE + NWAVE - 1) / NWAVE;
         constexpr int TB = TPW < 4 ? TPW : 4;
+        constexpr bool EVEN = NTILE % NWAVE == 0;  // no tile guard per wavefront
         const int c = lane & 15, g = lane >> 4, gh = g / G::PPL, gp = g % G::PPL;
 #pragma unroll
         for (int k0 = 0; k0 < TPW; k0 += TB) {
@@ -199,13 +200,13 @@ struct MfmaPairs {
                 for (int k = 0; k < TB; k++) {
                     const int tile = wave + (k0 + k) * NWAVE;
                     lp[k] = (tile * 16 + c) * G::LPC + gh;
-                    if (k0 + k < TPW && tile < NTILE)
+                    if (k0 + k < TPW && (EVEN || tile < NTILE))
                         bv[k] = *reinterpret_cast<const f32x4 *>(X + lp[k] * G::LSTRIDE + 4 * (gp ^ G::sw(lp[k] % F)));
                 }
 #pragma unroll
                 for (int k = 0; k < TB; k++) {
                     const int tile = wave + (k0 + k) * NWAVE;
-                    if (k0 + k < TPW && tile < NTILE) {
+                    if (k0 + k < TPW && (EVEN || tile < NTILE)) {
                         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                         for (int m = 0; m < 4; m++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(am[m], bv[k][m], acc, 0, 0, 0);
@@ -218,13 +219,13 @@ struct MfmaPairs {
                 for (int k = 0; k < TB; k++) {
                     const int tile = wave + (k0 + k) * NWAVE;
                     lp[k] = (tile * 16 + c) * G::LPC + gh;
-                    if (k0 + k < TPW && tile < NTILE)
+                    if (k0 + k < TPW && (EVEN || tile < NTILE))
                         bv[k] = *reinterpret_cast<const VT *>(X + lp[k] * G::LSTRIDE + 4 * (gp ^ G::sw(lp[k] % F)));
                 }
 #pragma unroll
                 for (int k = 0; k < TB; k++) {
                     const int tile = wave + (k0 + k) * NWAVE;
-                    if (k0 + k < TPW && tile < NTILE) {
+                    if (k0 + k < TPW && (EVEN || tile < NTILE)) {
                         const f32x4 z = {0.f, 0.f, 0.f, 0.f};
                         if constexpr (P == PBF16) cc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv[k], z, 0, 0, 0);
                         else cc[k] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bv[k], z, 0, 0, 0);
@@ -234,7 +235,7 @@ struct MfmaPairs {
 #pragma unroll
             for (int k = 0; k < TB; k++) {
                 const int tile = wave + (k0 + k) * NWAVE;
-                if (k0 + k < TPW && tile < NTILE) {
+                if (k0 + k < TPW && (EVEN || tile < NTILE)) {
                     float *y = Y + lp[k] * G::template ostride<P>() + 4 * gp;
                     if (P != P32 || 2 * gp < n) *reinterpret_cast<f32x2 *>(y) = f32x2{cc[k][0], cc[k][1]};
                     if (P != P32 || 2 * gp + 1 < n) *reinterpret_cast<f32x2 *>(y + 2) = f32x2{cc[k][2], cc[k][3]};
@@ -366,6 +367,37 @@ struct NoPitch {
 };
 
 // ---------------------------------------------------------------------------
+// Epilogue line buffers (face projection and volume integral), one direction
+// at a time.  Input: position-major FP64 Ein[k][line] for the lines
+// (cell, q|f, var, face node), odd pitch.  Volume output: FP64 Evol[i][line]
+// for the lines (cell, var, face node).
+// ---------------------------------------------------------------------------
+template <class Pde, int DIM, int N>
+struct EpiLayout {
+    using Sh = Shape<DIM, N>;
+    static constexpr int n = Sh::n, F = Sh::F, CPB = Sh::CPB, V = Pde::V;
+    static constexpr int NLV = CPB * V * F;
+    static constexpr int NLE = 2 * NLV;
+    static constexpr int NLPE = NLE | 1, NLPV = NLV | 1;
+    static constexpr size_t in_bytes = (size_t)n * NLPE * 8;
+    static constexpr size_t bytes = in_bytes + (size_t)n * NLPV * 8;
+};
+
+// LDS of the predictor's phases other than the Picard lines: the epilogue,
+// the non-conservative averages and the fused corrector.
+template <class Pde, int DIM, int N>
+struct RestLds {
+    using Sh = Shape<DIM, N>;
+    static constexpr size_t epi = EpiLayout<Pde, DIM, N>::bytes;
+    static constexpr size_t ncp = Pde::kNCP ? (size_t)Sh::CPB * DIM * Sh::S * 8 : 0;
+    static constexpr size_t corr = (size_t)Sh::CPB * DIM * 2 * Pde::V * Sh::F * 8;
+    static constexpr size_t bytes = epi > ncp ? (epi > corr ? epi : corr) : (ncp > corr ? ncp : corr);
+};
+
+// Workgroups of up to four wavefronts that fit a CU's 160 KB of LDS (at most 3).
+constexpr int lds_waves(size_t bytes) { return bytes * 3 <= 160 * 1024 ? 3 : (bytes * 2 <= 160 * 1024 ? 2 : 1); }
+
+// ---------------------------------------------------------------------------
 // Picard line buffers.
 //  FP64: lines numbered ((cb*DIM + j)*NZ + i)*F + f (block cell cb, direction
 //        j, i-th flux component of FluxSupport, face node f), position-major
@@ -390,30 +422,28 @@ struct PicardLayout {
     using G = PairGeom<n>;
     static constexpr int NP = (NZ + 1) / 2;
     static constexpr int NLPR = CPB * DIM * NP * F;
-    static constexpr int NTILE = (NLPR + 16 * G::LPC - 1) / (16 * G::LPC);
+    static constexpr size_t esz = PP == P64 ? 8 : sizeof(typename Store<PP>::T);
+    static constexpr size_t tile_bytes(int nt) {
+        return (size_t)nt * 16 * 16 * esz + (size_t)nt * 16 * G::LPC * G::template ostride<PP>() * 4;
+    }
+    // Tiles: rounded up to a whole number per wavefront, so that the tile
+    // loop needs no guard (the padding tiles read zeros and write outputs that
+    // are never read), where that adds at most an eighth more tiles and keeps
+    // the workgroups per CU; else the exact count.
+    static constexpr int NWAVE = Sh::TPB / 64;
+    static constexpr int NTILE0 = (NLPR + 16 * G::LPC - 1) / (16 * G::LPC);
+    static constexpr int NTILEP = (NTILE0 + NWAVE - 1) / NWAVE * NWAVE;
+    static constexpr size_t rest = RestLds<Pde, DIM, N>::bytes;
+    static constexpr bool PAD =
+        (NTILEP - NTILE0) * 8 <= NTILE0 &&
+        lds_waves(tile_bytes(NTILEP) > rest ? tile_bytes(NTILEP) : rest) ==
+            lds_waves(tile_bytes(NTILE0) > rest ? tile_bytes(NTILE0) : rest);
+    static constexpr int NTILE = PAD ? NTILEP : NTILE0;
     static constexpr int PSTRIDE = G::LSTRIDE * F;   // input elements between variable pairs
     static constexpr int POSTRIDE = G::template ostride<PP>() * F;  // output floats between variable pairs
-    static constexpr size_t esz = PP == P64 ? 8 : sizeof(typename Store<PP>::T);
     static constexpr size_t in_bytes = (size_t)NTILE * 16 * 16 * esz;
     static constexpr size_t out_bytes = (size_t)NTILE * 16 * G::LPC * G::template ostride<PP>() * 4;
     static constexpr size_t bytes = PP == P64 ? (size_t)n * NLP * 8 : in_bytes + out_bytes;
-};
-
-// ---------------------------------------------------------------------------
-// Epilogue line buffers (face projection and volume integral), one direction
-// at a time.  Input: position-major FP64 Ein[k][line] for the lines
-// (cell, q|f, var, face node), odd pitch.  Volume output: FP64 Evol[i][line]
-// for the lines (cell, var, face node).
-// ---------------------------------------------------------------------------
-template <class Pde, int DIM, int N>
-struct EpiLayout {
-    using Sh = Shape<DIM, N>;
-    static constexpr int n = Sh::n, F = Sh::F, CPB = Sh::CPB, V = Pde::V;
-    static constexpr int NLV = CPB * V * F;
-    static constexpr int NLE = 2 * NLV;
-    static constexpr int NLPE = NLE | 1, NLPV = NLV | 1;
-    static constexpr size_t in_bytes = (size_t)n * NLPE * 8;
-    static constexpr size_t bytes = in_bytes + (size_t)n * NLPV * 8;
 };
 
 // ---------------------------------------------------------------------------
@@ -421,30 +451,23 @@ struct EpiLayout {
 // ---------------------------------------------------------------------------
 template <class Pde, int DIM, int N, int PP>
 struct PredLds {
-    using Sh = Shape<DIM, N>;
-    static constexpr int V = Pde::V;
-    static constexpr int NV = Pde::kNCP ? V + 1 : V;
-    static constexpr int CPB = Sh::CPB, S = Sh::S;
     static constexpr size_t picard = PicardLayout<Pde, DIM, N, PP>::bytes;
-    static constexpr size_t epi = EpiLayout<Pde, DIM, N>::bytes;
-    static constexpr size_t ncp = Pde::kNCP ? (size_t)CPB * DIM * S * 8 : 0;
-    static constexpr size_t bytes0 = picard > epi ? picard : epi;
-    static constexpr size_t bytes1 = bytes0 > ncp ? bytes0 : ncp;
-    static constexpr size_t corr = (size_t)Sh::CPB * DIM * 2 * V * Sh::F * 8;  // fused corrector
-    static constexpr size_t bytes = bytes1 > corr ? bytes1 : corr;
+    static constexpr size_t rest = RestLds<Pde, DIM, N>::bytes;
+    static constexpr size_t bytes = picard > rest ? picard : rest;
 };
 
 // Target occupancy of the predictor (wavefronts per SIMD; a workgroup has at
 // most four wavefronts, one per SIMD): three (at most 168 registers per lane)
 // when the LDS holds three workgroups per CU, else two (256 registers) when it
 // holds two.  The latency of the two barriers per slice needs the third
-// wavefront: the FP64 3-D elastic order-5 kernel spills 124 bytes per lane at
-// this target and still runs 13 % faster than at two.
+// wavefront: the FP64 3-D elastic order-5 kernel spills a few registers at
+// this target (to scratch, outside the Picard loop) and still runs faster
+// than at two.
 template <class Pde, int DIM, int N, int PP>
 struct PredOcc {
     static constexpr size_t lds = PredLds<Pde, DIM, N, PP>::bytes;
     static constexpr bool fits = Shape<DIM, N>::TPB <= 256;
-    static constexpr int waves = !fits ? 1 : (lds * 3 <= 160 * 1024) ? 3 : (lds * 2 <= 160 * 1024 ? 2 : 1);
+    static constexpr int waves = !fits ? 1 : lds_waves(lds);
 };
 
 // For a linear flux with cell-constant coefficients and FP64 faces, the face
