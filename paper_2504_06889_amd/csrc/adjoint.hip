@@ -200,6 +200,7 @@ int adjoint_step(AdjointWork &w, const AdjointArgs &a, hipStream_t st, std::stri
     // halves only (aderdg_copy_faces of a linear PDE with FP64 faces)
     k.fwd_halves = a.fwdface ? 1 : 2;
     k.B = a.B;
+    k.st = a.st;
     k.pde = a.pde;
     k.ncell = a.ncell;
     for (int i = 0; i < 3; i++) k.cells[i] = a.cells[i];

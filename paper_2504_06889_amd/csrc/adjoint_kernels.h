@@ -45,6 +45,7 @@ struct AdjKArgs {
     const double *fwdface; // forward face data of the step [cell][dir][side][half][V][F]
     int fwd_halves;        // halves per face side in fwdface: 2 ([q|f]) or 1 (q only)
     const DevBasis *B;
+    const ScaledTime *st;  // the time operator scaled by -sigma for this dt
     PdeArgs pde;
     long ncell;
     int cells[3];
@@ -226,6 +227,7 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
     double *kbuf = fbuf + AL::NRI;                                           // [TPB] per-thread terms
 
     CBasis *B = (CBasis *)a.B;
+    CScaled *ST = (CScaled *)a.st;
     const int tid = threadIdx.x;
     const int cb = tid / S, s = tid % S;
     const long blk = xcd_block(blockIdx.x, gridDim.x);
@@ -361,7 +363,7 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
     for (int it = 1; it < iters; it++) {
 #pragma unroll
         for (int b0 = 0; b0 < n; b0 += SPI) fwd_group(b0, b0 + SPI <= n ? SPI : n - b0, false);
-        if (active) {
+        if (it < iters - 1 && active) {
 #pragma unroll
             for (int v = 0; v < V; v++) {
                 double r[n], rd[n];
@@ -372,27 +374,31 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
                 }
 #pragma unroll
                 for (int t = 0; t < n; t++) {
-                    double acc = 0.0, accd = 0.0;
+                    double acc = Qn[v], accd = 0.0;
 #pragma unroll
                     for (int b = 0; b < n; b++) {
-                        acc = fma(B->Atau[t][b], r[b], acc);
-                        accd = fma(B->Atau[t][b], rd[b], accd);
+                        acc = fma(ST->At[t][b], r[b], acc);
+                        accd = fma(ST->At[t][b], rd[b], accd);
                     }
-                    z[t][v] = fma(-a.sigma, acc, Qn[v]);
-                    zd[t][v] = -a.sigma * accd;
+                    z[t][v] = acc;
+                    zd[t][v] = accd;
                 }
             }
         }
     }
+    // time averages: after more than one iteration the rows hold h R_b (h dR_b/dK)
+    // of the last one and qbar = Q - sigma sum_b (sum_a w_a Atau[a][b]) h R_b (the
+    // weights sum to one), without forming the last iterate
     double qbar[V], qbard[V];
 #pragma unroll
     for (int v = 0; v < V; v++) {
-        qbar[v] = 0.0;
+        qbar[v] = iters > 1 ? Qn[v] : 0.0;
         qbard[v] = 0.0;
 #pragma unroll
         for (int t = 0; t < n; t++) {
-            qbar[v] = fma(B->w[t], z[t][v], qbar[v]);
-            qbard[v] = fma(B->w[t], zd[t][v], qbard[v]);
+            const double wt = iters > 1 ? ST->wA[t] : B->w[t];
+            qbar[v] = fma(wt, z[t][v], qbar[v]);
+            qbard[v] = fma(wt, zd[t][v], qbard[v]);
         }
     }
     __syncthreads();

@@ -750,7 +750,7 @@ static aderdg_status step_adjoint(aderdg_solver *s, double dt, double t, const d
                  "(ncell * dim * 2 * (dim + 1) * (order + 1)^(dim - 1) * 8 bytes)",
                  need, (size_t)kNoAllocScratchBytes);
     }
-    if (!a.fwdface) {  // the forward face data are recomputed with the predictor
+    {  // read by the adjoint's forward sweep and by the predictor that recomputes the face data
         const aderdg_status rs = scale_time(s, dt);
         if (rs != ADERDG_OK) return rs;
     }
