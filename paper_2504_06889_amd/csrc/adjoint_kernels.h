@@ -123,43 +123,6 @@ __device__ __forceinline__ void lines_inplace(XT *X, int nl, int NLP, MT Mat, Li
     }
 }
 
-// Pitch of the FP32 line buffer: as for FP64 rows, but 32-bit reads and
-// writes are served 32 lanes at a time on 32 four-byte banks (conflict when
-// two lanes' floats agree mod 32).
-template <int n, int DIM, int NZ, int CPB, int TPB>
-struct Fp32Pitch {
-    using P64 = Fp64Pitch<n, DIM, NZ, CPB, TPB>;
-    static constexpr int NL = P64::NL;
-    static constexpr int cost(const typename P64::Lanes &L, int P) {
-        int c = 0;
-        for (int w = 0; w < TPB / 64; w++)
-            for (int j = 0; j < DIM; j++)
-                for (int g = 0; g < 2; g++) {
-                    int cnt[32] = {};
-                    int mx = 0;
-                    for (int l = w * 64 + 32 * g; l < w * 64 + 32 * g + 32; l++) {
-                        if (L.k[l][j] < 0) continue;
-                        const int b = (L.k[l][j] * P + L.base[l][j]) & 31;
-                        mx = ++cnt[b] > mx ? cnt[b] : mx;
-                    }
-                    c += mx > 1 ? mx - 1 : 0;
-                }
-        return c;
-    }
-    static constexpr int best() {
-        const typename P64::Lanes L = P64::lanes();
-        int bp = NL | 1, bc = cost(L, NL | 1);
-        for (int P = NL; P < NL + 32; P++) {
-            const int c = cost(L, P);
-            if (c < bc) {
-                bc = c;
-                bp = P;
-            }
-        }
-        return bp;
-    }
-    static constexpr int value = best();
-};
 
 // Line slots per direction j and cell: 0: F_j[0] = K v_j, 1: F_j[1+j] = p/rho
 // (the only non-zero components of the acoustic flux), 2, 3: their

@@ -366,6 +366,44 @@ struct NoPitch {
     static constexpr int value = 1;
 };
 
+// Pitch of the FP32 line buffer: as for FP64 rows, but 32-bit reads and
+// writes are served 32 lanes at a time on 32 four-byte banks (conflict when
+// two lanes' floats agree mod 32).
+template <int n, int DIM, int NZ, int CPB, int TPB>
+struct Fp32Pitch {
+    using P64 = Fp64Pitch<n, DIM, NZ, CPB, TPB>;
+    static constexpr int NL = P64::NL;
+    static constexpr int cost(const typename P64::Lanes &L, int P) {
+        int c = 0;
+        for (int w = 0; w < TPB / 64; w++)
+            for (int j = 0; j < DIM; j++)
+                for (int g = 0; g < 2; g++) {
+                    int cnt[32] = {};
+                    int mx = 0;
+                    for (int l = w * 64 + 32 * g; l < w * 64 + 32 * g + 32; l++) {
+                        if (L.k[l][j] < 0) continue;
+                        const int b = (L.k[l][j] * P + L.base[l][j]) & 31;
+                        mx = ++cnt[b] > mx ? cnt[b] : mx;
+                    }
+                    c += mx > 1 ? mx - 1 : 0;
+                }
+        return c;
+    }
+    static constexpr int best() {
+        const typename P64::Lanes L = P64::lanes();
+        int bp = NL | 1, bc = cost(L, NL | 1);
+        for (int P = NL; P < NL + 32; P++) {
+            const int c = cost(L, P);
+            if (c < bc) {
+                bc = c;
+                bp = P;
+            }
+        }
+        return bp;
+    }
+    static constexpr int value = best();
+};
+
 // ---------------------------------------------------------------------------
 // Epilogue line buffers (face projection and volume integral), one direction
 // at a time.  Input: position-major FP64 Ein[k][line] for the lines
@@ -399,12 +437,14 @@ constexpr int lds_waves(size_t bytes) { return bytes * 3 <= 160 * 1024 ? 3 : (by
 
 // ---------------------------------------------------------------------------
 // Picard line buffers.
-//  FP64: lines numbered ((cb*DIM + j)*NZ + i)*F + f (block cell cb, direction
-//        j, i-th flux component of FluxSupport, face node f), position-major
-//        X[k][line] with the pitch NLP of Fp64Pitch, differentiated in place.
-//  other: line pairs LP = ((cb*DIM + j)*NP + p)*F + f for the component pairs
-//        (2p, 2p+1) (an odd NZ is padded with a zero component), in the
-//        MfmaPairs layout: the contraction format in, FP32 out.
+//  FP64 and FP32 (vector ALU): lines numbered ((cb*DIM + j)*NZ + i)*F + f
+//        (block cell cb, direction j, i-th flux component of FluxSupport,
+//        face node f), position-major X[k][line] with the bank-aware pitch NLP
+//        (Fp64Pitch, Fp32Pitch), differentiated in place.
+//  BF16/FP16 (matrix cores): line pairs LP = ((cb*DIM + j)*NP + p)*F + f for
+//        the component pairs (2p, 2p+1) (an odd NZ is padded with a zero
+//        component), in the MfmaPairs layout: the contraction format in, FP32
+//        out.
 // ---------------------------------------------------------------------------
 template <class Pde, int DIM, int N, int PP>
 struct PicardLayout {
@@ -412,10 +452,12 @@ struct PicardLayout {
     static constexpr int n = Sh::n, F = Sh::F, CPB = Sh::CPB;
     using FS = FluxSupport<Pde, DIM>;
     static constexpr int NZ = FS::NZ;
-    // FP64
+    // FP64 and FP32: the vector-ALU line pass
+    static constexpr bool VALU = PP == P64 || PP == P32;
     static constexpr int NL = CPB * DIM * NZ * F;
     static constexpr int NLP =
-        std::conditional<PP == P64, Fp64Pitch<n, DIM, NZ, CPB, Sh::TPB>, NoPitch>::type::value;
+        std::conditional<PP == P64, Fp64Pitch<n, DIM, NZ, CPB, Sh::TPB>,
+                         typename std::conditional<PP == P32, Fp32Pitch<n, DIM, NZ, CPB, Sh::TPB>, NoPitch>::type>::type::value;
     __device__ static constexpr int elem(int line, int k) { return k * NLP + line; }
     static constexpr int VSTRIDE = F;
     // lower formats
@@ -443,7 +485,7 @@ struct PicardLayout {
     static constexpr int POSTRIDE = G::template ostride<PP>() * F;  // output floats between variable pairs
     static constexpr size_t in_bytes = (size_t)NTILE * 16 * 16 * esz;
     static constexpr size_t out_bytes = (size_t)NTILE * 16 * G::LPC * G::template ostride<PP>() * 4;
-    static constexpr size_t bytes = PP == P64 ? (size_t)n * NLP * 8 : in_bytes + out_bytes;
+    static constexpr size_t bytes = VALU ? (size_t)n * NLP * (PP == P64 ? 8 : 4) : in_bytes + out_bytes;
 };
 
 // ---------------------------------------------------------------------------
@@ -714,7 +756,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
 #pragma unroll
     for (int j = 0; j < DIM; j++) {
         const int f = face_of<n, DIM>(s, j), k = coord<n>(s, j);
-        if constexpr (PP == P64) po[j] = PL::elem(((cb * DIM + j) * PL::NZ) * F + f, k);
+        if constexpr (PL::VALU) po[j] = PL::elem(((cb * DIM + j) * PL::NZ) * F + f, k);
         else po[j] = ((cb * DIM + j) * PL::NP) * F + f;
     }
     auto src_term = [&](int b) {
@@ -795,16 +837,23 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
             });
         }
     };
-    if constexpr (PP == P64) {
-        double *X = reinterpret_cast<double *>(smem);  // [n][NLP] position-major
-        // one slice: flux of the state qb at every node into the lines, the
-        // derivative along every line (in place), and the divergence at the
-        // node passed to sink(v, h R_v) in descending v
-        auto slice = [&](const double *qb, auto &&sink) __attribute__((always_inline)) {
+    if constexpr (PL::VALU) {
+        // FP64, or FP32 (inputs rounded to FP32, FP32 accumulation, the sum
+        // over the directions included; on the vector ALU, where the FP32
+        // matrix cores' four 16x16x4 steps per tile and wide operands cost more)
+        using XT = typename std::conditional<PP == P64, double, float>::type;
+        XT *X = reinterpret_cast<XT *>(smem);  // [n][NLP] position-major
+        // one slice: flux of the state q_b (rounded to XT) at every node into
+        // the lines, the derivative along every line (in place), and the
+        // divergence at the node passed to sink(v, h R_v) in descending v
+        auto slice = [&](const auto *qrow, auto &&sink) __attribute__((always_inline)) {
+            XT qb[V];
+#pragma unroll
+            for (int v = 0; v < V; v++) qb[v] = (XT)qrow[v];
             if (slot) {
 #pragma unroll
                 for (int j = 0; j < DIM; j++) {
-                    double Fv[V];
+                    XT Fv[V];
                     Pde::flux(coef, qb, j, Fv);
 #pragma unroll
                     for (int i = 0; i < PL::NZ; i++) {
@@ -815,14 +864,17 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
             }
             __syncthreads();
             for (int Ln = tid; Ln < PL::NL; Ln += TPB) {
-                double x[n];
+                XT x[n];
 #pragma unroll
                 for (int k = 0; k < n; k++) x[k] = X[k * PL::NLP + Ln];
 #pragma unroll
                 for (int i = 0; i < n; i++) {
-                    double y = 0.0;
+                    XT y = 0;
 #pragma unroll
-                    for (int k = 0; k < n; k++) y = fma(B->D[i][k], x[k], y);
+                    for (int k = 0; k < n; k++) {
+                        if constexpr (PP == P64) y = fma(B->D[i][k], x[k], y);
+                        else y = fmaf(B->Dp[P32][i][k], x[k], y);
+                    }
                     X[i * PL::NLP + Ln] = y;
                 }
             }
@@ -831,17 +883,21 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 // descending v: the non-conservative term of v >= 1 reads q_b[0]
 #pragma unroll
                 for (int v = V - 1; v >= 0; v--) {
-                    double r = 0.0;
+                    XT r = 0;
 #pragma unroll
                     for (int j = 0; j < DIM; j++) {
                         const int i = PL::FS::index(j, v);
                         if (i >= 0) r += X[po[j] + i * PL::VSTRIDE];
                     }
+                    double rr = (double)r;
                     if constexpr (Pde::kNCP) {
-                        if (v >= 1 && v <= DIM)
-                            r += coef.g * qb[0] * X[po[v - 1] + PL::FS::index(v - 1, V) * PL::VSTRIDE];
+                        if (v >= 1 && v <= DIM) {
+                            const XT eta = X[po[v - 1] + PL::FS::index(v - 1, V) * PL::VSTRIDE];
+                            if constexpr (PP == P64) rr += coef.g * qb[0] * eta;
+                            else rr += (double)((float)coef.g * qb[0] * eta);
+                        }
                     }
-                    sink(v, r);
+                    sink(v, rr);
                 }
             }
         };
