@@ -4,8 +4,8 @@
 //    Each thread keeps its node's space-time column (all time nodes, all
 //    variables) in registers.  Per Picard iteration and time slice b the
 //    pointwise fluxes F_j(q_b) are written to LDS, every 1-D line is
-//    differentiated (D along x, y, z: in place in FP64 on the vector ALU, or
-//    on the matrix cores in FP32/BF16/FP16 with FP32 accumulation), and the
+//    differentiated (D along x, y, z: in place on the vector ALU in FP64 or
+//    FP32, or on the matrix cores in BF16/FP16 with FP32 accumulation), and the
 //    owner thread folds the divergence into the FP64 Picard update
 //    q_a <- Q - dt sum_b Atau[a][b] R_b (eq. Picard at the nodes); for a
 //    linear PDE the Cauchy-Kowalevskaya procedure can replace the iteration
@@ -125,8 +125,8 @@ __device__ __forceinline__ uint32_t pack2(float lo, float hi) {
 }
 
 // ---------------------------------------------------------------------------
-// Matrix-core derivative of variable pairs, inputs in format P (FP32, BF16 or
-// FP16), FP32 accumulation.  Data: for every line pair LP (one line geometry,
+// Matrix-core derivative of variable pairs, inputs in format P (BF16 or FP16),
+// FP32 accumulation.  Data: for every line pair LP (one line geometry,
 // two variables), NPOS position slots (8, or 4 when n <= 4) x 2 variables,
 // position pairs swizzled by the face node f of the line: element
 // LP*2*NPOS + 4*((k/2) ^ sw(f)) + 2*(k%2) + var.  One 16x16 tile takes
@@ -134,13 +134,12 @@ __device__ __forceinline__ uint32_t pack2(float lo, float hi) {
 // position, variable)); the constant A operand holds D on the interleaved
 // block diagonal (row (line pair, i, var), column (line pair, k, var)), so a
 // C column is the derivative of both variables of its line pairs.  FP32
-// results go to Y[LP*OSTRIDE + 2*i + var] (ostride() below; in FP32 the
-// padding positions are not stored).  Lane layouts (64 lanes,
-// 16x16xK): A[row = lane%16][k], B[k][col = lane%16],
+// results go to Y[LP*OSTRIDE + 2*i + var] (OSTRIDE below).  Lane layouts (64
+// lanes, 16x16x16): A[row = lane%16][k], B[k][col = lane%16],
 // C[row = 4*(lane/16) + e][col], with lane group g = lane/16 holding
-// k = 4g..4g+3 (16-bit formats), or one k per instruction ordered so that its
-// four values are one 16-byte load (FP32).  The input swizzle spreads the
-// owner writes over the LDS banks.
+// k = 4g..4g+3.  The input swizzle spreads the owner writes over the LDS
+// banks.  (FP32 contractions run on the vector ALU: the FP32 matrix cores take
+// four 16x16x4 steps per tile on operands twice as wide.)
 // ---------------------------------------------------------------------------
 template <int n>
 struct PairGeom {
@@ -150,24 +149,20 @@ struct PairGeom {
     static constexpr int LSTRIDE = 2 * NPOS;      // input elements per line pair
     // output floats per line pair, an odd number of float pairs (the 16 lanes
     // of a 64-bit store then cover the 32 banks once): all NPOS positions of
-    // both variables, or, in FP32 (whose larger operands would otherwise keep
-    // a third workgroup out of a CU's LDS), only the n real positions, the
-    // padding rows not stored.  Measured: trimming the 16-bit formats' rows
-    // costs 10 % (3-D elastic N=5) although it saves LDS traffic.
-    template <int P>
-    static constexpr int ostride() { return P == P32 ? 2 * ((n + 1) | 1) : 2 * NPOS + 2; }
+    // both variables.  Measured: not storing the padding rows costs 10 % (3-D
+    // elastic N=5) although it saves LDS traffic.
+    static constexpr int OSTRIDE = 2 * NPOS + 2;
     __device__ static constexpr int sw(int f) { return (f >> 2) & (PPL - 1); }
     __device__ static int in_off(int lp, int f, int k) { return lp * LSTRIDE + 4 * ((k >> 1) ^ sw(f)) + 2 * (k & 1); }
-    template <int P>
-    __device__ static int out_off(int lp, int k) { return lp * ostride<P>() + 2 * k; }
+    __device__ static int out_off(int lp, int k) { return lp * OSTRIDE + 2 * k; }
 };
 
 template <int P, int n>
 struct MfmaPairs {
+    static_assert(P == PBF16 || P == PF16, "matrix-core pairs take a 16-bit format");
     using T = typename Store<P>::T;
     using VT = typename std::conditional<P == PBF16, i16x4, f16x4>::type;
-    VT a;          // 16-bit formats: A operand
-    float am[4];   // FP32: A operand of each of the four 16x16x4 steps
+    VT a;  // A operand
 
     using G = PairGeom<n>;
     template <class MT>
@@ -178,8 +173,7 @@ struct MfmaPairs {
         for (int e = 0; e < 4; e++) {
             const int k = 4 * g + e, hk = k / G::LSTRIDE, kp = (k % G::LSTRIDE) >> 1;
             const float val = (hr == hk && (k & 1) == vb && i < n && kp < n) ? M[i][kp] : 0.0f;
-            if constexpr (P == P32) am[e] = val;
-            else if constexpr (P == PBF16) a[e] = __builtin_bit_cast(short, round_to<PBF16>(val));
+            if constexpr (P == PBF16) a[e] = __builtin_bit_cast(short, round_to<PBF16>(val));
             else a[e] = round_to<PF16>(val);
         }
     }
@@ -194,51 +188,30 @@ struct MfmaPairs {
         for (int k0 = 0; k0 < TPW; k0 += TB) {
             f32x4 cc[TB];
             int lp[TB];
-            if constexpr (P == P32) {
-                f32x4 bv[TB];
+            VT bv[TB];
 #pragma unroll
-                for (int k = 0; k < TB; k++) {
-                    const int tile = wave + (k0 + k) * NWAVE;
-                    lp[k] = (tile * 16 + c) * G::LPC + gh;
-                    if (k0 + k < TPW && (EVEN || tile < NTILE))
-                        bv[k] = *reinterpret_cast<const f32x4 *>(X + lp[k] * G::LSTRIDE + 4 * (gp ^ G::sw(lp[k] % F)));
-                }
+            for (int k = 0; k < TB; k++) {
+                const int tile = wave + (k0 + k) * NWAVE;
+                lp[k] = (tile * 16 + c) * G::LPC + gh;
+                if (k0 + k < TPW && (EVEN || tile < NTILE))
+                    bv[k] = *reinterpret_cast<const VT *>(X + lp[k] * G::LSTRIDE + 4 * (gp ^ G::sw(lp[k] % F)));
+            }
 #pragma unroll
-                for (int k = 0; k < TB; k++) {
-                    const int tile = wave + (k0 + k) * NWAVE;
-                    if (k0 + k < TPW && (EVEN || tile < NTILE)) {
-                        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                        for (int m = 0; m < 4; m++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(am[m], bv[k][m], acc, 0, 0, 0);
-                        cc[k] = acc;
-                    }
-                }
-            } else {
-                VT bv[TB];
-#pragma unroll
-                for (int k = 0; k < TB; k++) {
-                    const int tile = wave + (k0 + k) * NWAVE;
-                    lp[k] = (tile * 16 + c) * G::LPC + gh;
-                    if (k0 + k < TPW && (EVEN || tile < NTILE))
-                        bv[k] = *reinterpret_cast<const VT *>(X + lp[k] * G::LSTRIDE + 4 * (gp ^ G::sw(lp[k] % F)));
-                }
-#pragma unroll
-                for (int k = 0; k < TB; k++) {
-                    const int tile = wave + (k0 + k) * NWAVE;
-                    if (k0 + k < TPW && (EVEN || tile < NTILE)) {
-                        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-                        if constexpr (P == PBF16) cc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv[k], z, 0, 0, 0);
-                        else cc[k] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bv[k], z, 0, 0, 0);
-                    }
+            for (int k = 0; k < TB; k++) {
+                const int tile = wave + (k0 + k) * NWAVE;
+                if (k0 + k < TPW && (EVEN || tile < NTILE)) {
+                    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+                    if constexpr (P == PBF16) cc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv[k], z, 0, 0, 0);
+                    else cc[k] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bv[k], z, 0, 0, 0);
                 }
             }
 #pragma unroll
             for (int k = 0; k < TB; k++) {
                 const int tile = wave + (k0 + k) * NWAVE;
                 if (k0 + k < TPW && (EVEN || tile < NTILE)) {
-                    float *y = Y + lp[k] * G::template ostride<P>() + 4 * gp;
-                    if (P != P32 || 2 * gp < n) *reinterpret_cast<f32x2 *>(y) = f32x2{cc[k][0], cc[k][1]};
-                    if (P != P32 || 2 * gp + 1 < n) *reinterpret_cast<f32x2 *>(y + 2) = f32x2{cc[k][2], cc[k][3]};
+                    float *y = Y + lp[k] * G::OSTRIDE + 4 * gp;
+                    *reinterpret_cast<f32x2 *>(y) = f32x2{cc[k][0], cc[k][1]};
+                    *reinterpret_cast<f32x2 *>(y + 2) = f32x2{cc[k][2], cc[k][3]};
                 }
             }
         }
@@ -466,7 +439,7 @@ struct PicardLayout {
     static constexpr int NLPR = CPB * DIM * NP * F;
     static constexpr size_t esz = PP == P64 ? 8 : sizeof(typename Store<PP>::T);
     static constexpr size_t tile_bytes(int nt) {
-        return (size_t)nt * 16 * 16 * esz + (size_t)nt * 16 * G::LPC * G::template ostride<PP>() * 4;
+        return (size_t)nt * 16 * 16 * esz + (size_t)nt * 16 * G::LPC * G::OSTRIDE * 4;
     }
     // Tiles: rounded up to a whole number per wavefront, so that the tile
     // loop needs no guard (the padding tiles read zeros and write outputs that
@@ -482,9 +455,9 @@ struct PicardLayout {
             lds_waves(tile_bytes(NTILE0) > rest ? tile_bytes(NTILE0) : rest);
     static constexpr int NTILE = PAD ? NTILEP : NTILE0;
     static constexpr int PSTRIDE = G::LSTRIDE * F;   // input elements between variable pairs
-    static constexpr int POSTRIDE = G::template ostride<PP>() * F;  // output floats between variable pairs
+    static constexpr int POSTRIDE = G::OSTRIDE * F;  // output floats between variable pairs
     static constexpr size_t in_bytes = (size_t)NTILE * 16 * 16 * esz;
-    static constexpr size_t out_bytes = (size_t)NTILE * 16 * G::LPC * G::template ostride<PP>() * 4;
+    static constexpr size_t out_bytes = (size_t)NTILE * 16 * G::LPC * G::OSTRIDE * 4;
     static constexpr size_t bytes = VALU ? (size_t)n * NLP * (PP == P64 ? 8 : 4) : in_bytes + out_bytes;
 };
 
@@ -931,7 +904,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         for (int j = 0; j < DIM; j++) {
             const int f = face_of<n, DIM>(s, j), k = coord<n>(s, j);
             io[j] = PL::G::in_off(po[j], f, k);
-            oo[j] = PL::G::template out_off<PP>(po[j], k);
+            oo[j] = PL::G::out_off(po[j], k);
         }
         __syncthreads();
         // One contraction pass on the matrix cores: the owners write the flux
@@ -950,8 +923,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 for (int p = 0; p < PL::NP; p++) {
                     T *dst = FbB + io[j] + p * PL::PSTRIDE;
                     const float f0 = comp_val(PL::FS::comp(j, 2 * p)), f1 = comp_val(PL::FS::comp(j, 2 * p + 1));
-                    if constexpr (PP == P32) *reinterpret_cast<f32x2 *>(dst) = f32x2{f0, f1};
-                    else *reinterpret_cast<uint32_t *>(dst) = pack2<PP>(f0, f1);
+                    *reinterpret_cast<uint32_t *>(dst) = pack2<PP>(f0, f1);
                 }
             }
         };
@@ -1050,9 +1022,8 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
         // Volume integral on the matrix cores when its format is the
         // predictor's 16-bit format (linear flux: fbar_j = F_j(qbar), FP64,
         // rounded to the format; Kxi in the format; FP32 accumulation, the sum
-        // over the directions included).  In FP32 the four 16x16x4 steps per
-        // tile and the doubled LDS traffic cost more than the vector ALU path.
-        if constexpr (FR && PP != P32) {
+        // over the directions included).
+        if constexpr (FR) {
             if (vp == PP) {
                 MfmaPairs<PP, n> mk;
                 mk.init(B->Kxip[PP], lane);
