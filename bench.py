@@ -7,9 +7,9 @@ dt = C h / (d (2N+1) lambda_max).  One step = predictor (Picard iteration),
 face projection, volume integral, Rusanov flux and corrector over all cells.
 
 The same K steps are timed for the all-FP64 path and for the predictor and
-volume contractions in FP32, BF16 and FP16 on the matrix cores (FP32
-accumulate; Picard time operator, time averages, flux/corrector and state in
-FP64).  `value` is the FP16 variant's cell-DOF updates/s (DOF = cells * n^3 * 9
+volume contractions in FP32 (vector ALU), BF16 and FP16 (matrix cores), with
+FP32 accumulation; Picard time operator, time averages, flux/corrector and
+state in FP64.  `value` is the FP16 variant's cell-DOF updates/s (DOF = cells * n^3 * 9
 per step); every variant's throughput, speed-up over FP64 and L2 error
 (eq. L2gauss norm, relative) against the FP64 GPU run and the exact solution
 are in `runs`.  Inputs are resident in HBM before the timed region.
@@ -30,8 +30,7 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks: FP64 vector (= FP64 matrix) 78.6 TFLOP/s, FP32 157.3
 # TFLOP/s (vector, packed; dense matrix), dense BF16/FP16 matrix 2.5 PFLOP/s,
 # HBM3E 8 TB/s; 1024 SIMDs (256 CUs) at 2.4 GHz.
-PEAK = {"fp64": 78.6e12, "fp32_valu": 157.3e12, "mfma_fp32": 157.3e12, "mfma_bf16": 2.5e15,
-        "mfma_fp16": 2.5e15, "hbm": 8.0e12}
+PEAK = {"fp64": 78.6e12, "fp32_valu": 157.3e12, "mfma_bf16": 2.5e15, "mfma_fp16": 2.5e15, "hbm": 8.0e12}
 CLOCK_HZ = 2.4e9
 SIMDS = 1024
 TOL = {"fp64": 1e-10, "fp32": 1e-6, "fp16": 1e-3, "bf16": 1e-2}
@@ -45,8 +44,8 @@ def flux_flops(pde, d):
 
 def predictor_flops(pde, d, N, V, I):
     """Algorithmic flops per cell of one predictor launch (sum-factorised, no
-    padding): returns (contraction flops that go to the matrix cores in the
-    mixed path, FP64 vector flops, pointwise-flux flops)."""
+    padding): returns (contraction flops -- on the matrix cores in BF16/FP16, on
+    the vector ALU in FP32 and FP64 --, FP64 vector flops, pointwise-flux flops)."""
     n = N + 1
     S = n ** d
     ST = n * S
@@ -137,9 +136,10 @@ def measured_mfma_busy(workload="elastic3d_n5_64"):
 def roofline(pde, d, N, V, I, ncell, t, prec, q_only, traffic=None, mfma_busy=None, state_bytes=8):
     """Roofline entry of one fused launch (corrector of the previous step + predictor)
     taking t seconds: the achieved fraction of each published peak the launch's
-    algorithmic work touches -- HBM bytes / 8 TB/s, the matrix-core contraction flops
-    / the format's dense matrix peak (lower formats), the FP64 vector flops / 78.6
-    TFLOP/s (in FP64 every flop) -- and the binding one (largest fraction) as
+    algorithmic work touches -- HBM bytes / 8 TB/s, the contraction flops / the
+    format's dense matrix peak (BF16, FP16) or the FP32 vector peak (FP32, whose
+    contractions run on the vector ALU), the FP64 vector flops / 78.6 TFLOP/s (in
+    FP64 every flop) -- and the binding one (largest fraction) as
     bound/achieved/peak/frac.  design_bound: the launch time if every unit ran at its
     peak at once (max over units) and, for comparison, the blended sum of the unit
     times.  traffic: HBM bytes per launch measured with rocprofv3 counters (or None);
@@ -154,24 +154,25 @@ def roofline(pde, d, N, V, I, ncell, t, prec, q_only, traffic=None, mfma_busy=No
         fr["fp64_valu"] = total / t / PEAK["fp64"]
         times["fp64_valu"] = total / PEAK["fp64"]
     else:
-        fr["mfma_" + prec] = mf * ncell / t / PEAK["mfma_" + prec]
+        ck = "fp32_valu" if prec == "fp32" else "mfma_" + prec
+        fr[ck] = mf * ncell / t / PEAK[ck]
         fr["fp64_valu"] = v64 * ncell / t / PEAK["fp64"]
-        times["mfma_" + prec] = mf * ncell / PEAK["mfma_" + prec]
+        times[ck] = mf * ncell / PEAK[ck]
         times["fp64_valu"] = v64 * ncell / PEAK["fp64"] + fl * ncell / PEAK["fp32_valu"]
     key = max(fr, key=fr.get)
     if key == "hbm":
         achieved, peak, unit = hbm / t / 1e9, PEAK["hbm"] / 1e9, "GB/s"
         bound = "hbm"
-    elif key.startswith("mfma"):
+    elif key.startswith("mfma") or key == "fp32_valu":
         achieved, peak, unit = mf * ncell / t / 1e12, PEAK[key] / 1e12, "TFLOP/s"
-        bound = "mfma"
+        bound = "mfma" if key.startswith("mfma") else "alu"
     else:
         work = total if prec == "fp64" else v64 * ncell
         achieved, peak, unit = work / t / 1e12, PEAK["fp64"] / 1e12, "TFLOP/s"
         bound = "alu"
     out = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
            "traffic": traffic, "fractions": fr,
-           "flops_per_launch": total, "mfma_flops_per_launch": (mf * ncell if prec != "fp64" else 0),
+           "flops_per_launch": total, "mfma_flops_per_launch": (mf * ncell if prec in ("bf16", "fp16") else 0),
            "fp64_flops_per_launch": total if prec == "fp64" else v64 * ncell,
            "hbm_bytes_per_launch": hbm, "launch_ms": 1e3 * t,
            "design_bound": {"max_unit_ms": 1e3 * max(times.values()), "blended_ms": 1e3 * sum(times.values()),
