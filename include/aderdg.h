@@ -62,7 +62,8 @@ typedef enum { ADERDG_ACOUSTIC = 0, ADERDG_ELASTIC = 1, ADERDG_EULER = 2, ADERDG
  *               arithmetic is unchanged.  get/set_state still take FP64.
  * In a lower precision the contraction inputs (data and matrix) are rounded
  * to that format (round-to-nearest-even) and the products are accumulated in
- * FP32 (matrix cores for PREDICTOR and VOLUME); the Picard time operator, the
+ * FP32 (matrix cores for PREDICTOR and VOLUME in BF16/FP16, the vector ALU in
+ * FP32); the Picard time operator, the
  * time-average weights and every accumulation into the state stay FP64.  */
 typedef enum { ADERDG_K_PREDICTOR = 0, ADERDG_K_VOLUME = 1, ADERDG_K_FLUX = 2, ADERDG_K_STORAGE = 3 } aderdg_kernel;
 typedef enum { ADERDG_FP64 = 0, ADERDG_FP32 = 1, ADERDG_BF16 = 2, ADERDG_FP16 = 3 } aderdg_prec;
