@@ -657,6 +657,12 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
 
     CBasis *B = (CBasis *)a.B;
     CScaled *ST = (CScaled *)a.st;
+    // Issue priority: the wavefronts of a SIMD belong to different workgroups;
+    // the phases bounded by barriers and memory latency (corrector, time
+    // slices, epilogue) run at priority 2, the long FP64 Picard updates
+    // (vector ALU only, no barrier) at 0, so that an update fills the issue
+    // slots the other phases leave and does not delay a workgroup's barrier.
+    __builtin_amdgcn_s_setprio(2);
     const int tid = threadIdx.x;
     const int cb = tid / S, s = tid % S;
     const long blk = xcd_block(blockIdx.x, gridDim.x);
@@ -764,6 +770,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
     // instead of n^2 + n (the same value up to FP64 rounding).
     constexpr bool QDIRECT = Pde::kLinear && !Pde::kNCP;
     auto update = [&](bool last) __attribute__((always_inline)) {
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int v = 0; v < V; v++) {
             double r[n];
@@ -787,6 +794,7 @@ __attribute__((amdgpu_waves_per_eu(PredOcc<Pde, DIM, N, PP>::waves, 8))) void k_
                 z[t][v] = (RowT)acc;
             }
         }
+        __builtin_amdgcn_s_setprio(2);
     };
     // Cauchy-Kowalevskaya procedure (linear flux, no source): the Taylor terms
     // T_k = dt^k/k! d^kq/dt^k from T_0 = Qn, T_k = -(sigma/k) h R(T_{k-1}),
