@@ -191,6 +191,9 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
 
     CBasis *B = (CBasis *)a.B;
     CScaled *ST = (CScaled *)a.st;
+    // issue priority as in the predictor: 2 for the phases bounded by barriers
+    // and memory, 0 for the FP64 time-operator blocks (vector ALU only)
+    __builtin_amdgcn_s_setprio(2);
     const int tid = threadIdx.x;
     const int cb = tid / S, s = tid % S;
     const long blk = xcd_block(blockIdx.x, gridDim.x);
@@ -327,6 +330,7 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
 #pragma unroll
         for (int b0 = 0; b0 < n; b0 += SPI) fwd_group(b0, b0 + SPI <= n ? SPI : n - b0, false);
         if (it < iters - 1 && active) {
+            __builtin_amdgcn_s_setprio(0);
 #pragma unroll
             for (int v = 0; v < V; v++) {
                 double r[n], rd[n];
@@ -347,6 +351,7 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
                     zd[t][v] = accd;
                 }
             }
+            __builtin_amdgcn_s_setprio(2);
         }
     }
     // time averages: after more than one iteration the rows hold h R_b (h dR_b/dK)
@@ -508,6 +513,7 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
     // the rows to Rbar_b = -dt sum_a Atau[a][b] rh_a
     auto adj_map = [&]() __attribute__((always_inline)) {
         if (!active) return;
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int v = 0; v < V; v++) {
             double tmp[n];
@@ -521,6 +527,7 @@ __global__ __launch_bounds__((Shape<DIM, N>::TPB)) __attribute__((amdgpu_waves_p
                 rh[b][v] = -a.dt * r;
             }
         }
+        __builtin_amdgcn_s_setprio(2);
     };
     // One line pass over the slices b0 .. b0+nsl-1; first: the FP64 kernel's
     // single pass of the first iteration.
